@@ -1,0 +1,171 @@
+"""Pins of the oracle's time stepping (streaming, conservation, the noise-free
+limit, equilibrium statistics) against the paper's stated results and
+closed forms.  CPU only; sized to run in seconds."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_16486_amd import workloads as W
+
+
+def _state(q, shape, seed, umax=0.05, amp=1e-3):
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, seed, umax=umax, dims=2 if q == 9 else 3)
+    return O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, seed + 1, amp)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (5, 4)), (27, (3, 4, 5))])
+def test_run_is_collide_then_stream(q, shape):
+    """orc_run equals per-site collisions (normals keyed by site and step)
+    followed by f_i(x + c_i) = f*_i(x) with periodic wrap (eq. streaming),
+    written here with numpy.roll."""
+    c, _ = O.lattice(q)
+    nx, ny, nz = W.shape3(shape)
+    f = _state(q, shape, 4)
+    lam = np.linspace(0.6, 1.9, q)
+    seed, replica, kT = 99, 5, 2e-3
+    g = f.copy()
+    O.run(q, shape, g, kT, lam, seed, replica, step0=3, nsteps=2)
+    h = f.copy()
+    for step in (3, 4):
+        fs = np.zeros_like(h)
+        for s in range(h.shape[1]):
+            eta = O.normals(q, seed, replica, step, s)
+            fs[:, s] = O.collide_site(q, h[:, s], eta, kT, lam)["fstar"]
+        for i in range(q):
+            grid = fs[i].reshape(nz, ny, nx)
+            grid = np.roll(grid, shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+            h[i] = grid.ravel()
+    assert np.allclose(g, h, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (32, 24)), (27, (8, 6, 10))])
+def test_run_conserves_mass_and_momentum(q, shape):
+    f = _state(q, shape, 8)
+    st = O.run(q, shape, f, 1e-3, O.paper_lambda(q, 1.6), seed=3, nsteps=100)
+    mass = st[:, 1]
+    assert np.ptp(mass) / mass[0] < 1e-13
+    mom = st[:, 2:5]
+    assert np.abs(mom - mom[0]).max() / mass[0] < 1e-14
+
+
+@pytest.mark.parametrize("q,shape", [(9, (16, 12)), (27, (6, 5, 4))])
+def test_zero_noise_rest_state_is_exact(q, shape):
+    """Test 1: with kT = 0 a fluid at rest stays at rest to machine precision
+    (the LU back-substitution leaves rounding-level velocities)."""
+    _, w = O.lattice(q)
+    n = W.n_sites(shape)
+    f = O.init_equilibrium(q, n, rho0=1.0)
+    st = O.run(q, shape, f, 0.0, O.paper_lambda(q, 1.25), seed=1, nsteps=50)
+    assert np.abs(f - w[:, None]).max() < 1e-15
+    assert np.abs(st[:, 5:8]).max() / n < 1e-16
+    assert np.abs(st[:, 8:11]).max() / n < 1e-31
+
+
+def test_equipartition_config1():
+    """Test 3 on a 64x64 D2Q9 box (rho0 = 1, tau = 0.8, kT = 1e-4, seed 1, 2000
+    steps): <u_a^2> = kT/rho0 (1 - 1/N) for both components; the per-step
+    RMS deviation is the white-noise value sqrt(2/N) kT/rho0, which is also
+    the size of the RMS printed in Table 2 (sqrt(2/200^2) kT = 2.4e-6 at
+    kT = 1/3000); density and momentum variances are 3 rho0 kT and rho0 kT."""
+    q, shape, kT = 9, (64, 64), 1e-4
+    n = W.n_sites(shape)
+    f = O.init_equilibrium(q, n, rho0=1.0)
+    st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), seed=1, nsteps=2000)
+    target = kT * (1 - 1 / n)
+    ux2, uy2 = st[200:, 8] / n, st[200:, 9] / n
+    assert abs(ux2.mean() / target - 1) < 0.015
+    assert abs(uy2.mean() / target - 1) < 0.015
+    e = 0.5 * (ux2 + uy2)
+    rms = np.sqrt(((e - kT) ** 2).mean())
+    assert 0.6 < rms / (math.sqrt(1.0 / n) * kT) < 1.6
+    # <u_a> ~ 0 (Test 3); only sum rho u is conserved, so sum u fluctuates
+    # at O(sqrt(N) kT), far below the thermal speed sqrt(kT)
+    assert np.abs(st[:, 5:7]).max() / n < 0.01 * kT ** 0.5
+    assert np.abs(st[:, 2:4]).max() / n < 1e-14
+    assert np.all(st[:, 11] == 0)
+    c, _ = O.lattice(q)
+    rho = f.sum(axis=0)
+    j = c[:, :2].T @ f
+    assert abs(rho.var() / (3 * kT) - 1) < 0.1
+    assert abs(j.var(axis=1).mean() / kT - 1) < 0.1
+    # Gaussian velocity statistics (Test 7, velocity PDFs)
+    u = j / rho
+    from scipy import stats
+    for a in range(2):
+        assert abs(stats.kurtosis(u[a], fisher=False) - 3) < 0.3
+
+
+@pytest.mark.parametrize("kT,rho0,tau", [(1e-5, 1.0, 0.8), (1e-3, 1.0, 0.8), (1e-4, 0.5, 0.8),
+                                         (1e-4, 2.0, 0.8), (1e-4, 1.0, 0.6), (1e-4, 1.0, 2.0)])
+def test_equipartition_scalings(kT, rho0, tau):
+    """Tests 4-6: <u_a^2> = kT/rho0 for every kT, rho0 and tau."""
+    q, shape = 9, (32, 32)
+    n = W.n_sites(shape)
+    f = O.init_equilibrium(q, n, rho0=rho0)
+    st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / tau), seed=7, nsteps=1500)
+    target = kT / rho0 * (1 - 1 / n)
+    r = st[300:, 8:10].mean(axis=0) / n / target
+    # nonlinear shift of order +9 kT/rho0 at the largest kT/rho0 (1e-3)
+    assert np.abs(r - 1).max() < 0.03 + 9 * kT / rho0
+
+
+def test_equipartition_d3q27_anisotropic_box():
+    """Test 7: isotropic equipartition on an anisotropic periodic box."""
+    q, shape, kT = 27, (6, 10, 14), 1e-4
+    n = W.n_sites(shape)
+    f = O.init_equilibrium(q, n, rho0=1.0)
+    st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), seed=5, nsteps=1200)
+    r = st[200:, 8:11].mean(axis=0) / n / (kT * (1 - 1 / n))
+    assert np.abs(r - 1).max() < 0.03
+    assert np.ptp(r) < 0.03
+
+
+@pytest.mark.parametrize("tau", [0.5, 0.5001, 0.501])
+def test_stable_near_tau_half(tau):
+    """Test 6: the CM scheme stays finite at and near tau = 0.5."""
+    q, shape, kT = 9, (32, 32), 1.0 / 3000
+    n = W.n_sites(shape)
+    f = O.init_equilibrium(q, n, rho0=1.0)
+    st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / tau), seed=2, nsteps=800)
+    assert np.all(st[:, 11] == 0)
+    assert np.all(np.isfinite(f))
+    r = st[400:, 8:10].mean() / n / kT
+    assert 0.85 < r < 1.15
+
+
+def test_nonfinite_is_counted():
+    """Rates outside (0, 2) make phi imaginary: the run reports non-finite
+    sites instead of silently continuing."""
+    q, shape = 9, (8, 8)
+    f = O.init_equilibrium(q, 64, rho0=1.0)
+    lam = np.full(q, 2.5)
+    st = O.run(q, shape, f, 1e-4, lam, seed=2, nsteps=3)
+    assert st[-1, 11] == 64
+
+
+def _tg_error(n, tau, u0=1e-3):
+    q, shape = 9, (n, n)
+    nu = (tau - 0.5) / 3.0
+    kappa = 2 * math.pi / n
+    u = W.taylor_green(shape, u0)
+    f = O.init_equilibrium(q, n * n, rho0=1.0, u=u)
+    steps = int(round(0.25 * n * n))
+    O.run(q, shape, f, 0.0, O.paper_lambda(q, 1 / tau), seed=0, nsteps=steps)
+    c, _ = O.lattice(q)
+    rho = f.sum(axis=0)
+    un = (c[:, :2].T @ f) / rho
+    ua = u[:2] * math.exp(-2 * nu * kappa ** 2 * steps)
+    return np.linalg.norm(un - ua) / np.linalg.norm(ua)
+
+
+def test_taylor_green_second_order():
+    """Test 2: without noise the Taylor-Green vortex decays as
+    exp(-2 nu kappa^2 t) and the error converges at second order."""
+    e16, e32, e64 = (_tg_error(n, 0.8) for n in (16, 32, 64))
+    assert e32 < 0.01
+    slope1 = math.log(e16 / e32, 2)
+    slope2 = math.log(e32 / e64, 2)
+    assert 1.7 < slope1 < 2.3 and 1.7 < slope2 < 2.3
