@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused fluctuating central-moment LBM step on one MI355X.
+
+Workload (the headline one): D3Q27, 256^3 periodic box, rho0 = 1, tau = 0.8,
+kT = 1e-4, Philox seed 1, started at rest; populations stored as FP32
+deviations f_i - w_i rho0, FP32 collision, per-step FP64 statistics.  A step
+is one pass of the whole path: pull streaming, moments, noise, collision,
+back transformation, store, and the statistics reduction.
+
+Prints one JSON line with the throughput in GLUPS (10^9 lattice-site updates
+per second), the HBM roofline of the fused-step kernel, FP16/BF16-storage
+variants and their <u^2> deviation from the FP32 run (same noise), and the
+CPU oracle's throughput on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+Q = 27
+SHAPE = (256, 256, 256)
+TAU, KT, RHO0, SEED = 0.8, 1e-4, 1.0, 1
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def bytes_per_site(storage):
+    # every population read once and written once per step
+    return 2 * Q * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_storage(storage, steps, warmup, stream, torch):
+    from paper_2602_16486_amd import Lattice
+    n = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    with Lattice(Q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
+                 stream=stream.cuda_stream, series_capacity=8192) as lat:
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        lat.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        # live per-kernel duration of the fused step (HIP events around each
+        # launch on the lattice's stream), same state, direct launches
+        kprof = 20
+        kernel_ms = lat.profile_steps(kprof) / kprof
+        st = lat.stats()
+    ms_step = ms / steps
+    glups = n / (ms_step * 1e-3) / 1e9
+    # equipartition over the recorded steps after the first 30 (warm-up)
+    u2 = st[30:, 8:11].sum(axis=1) / (3 * n)
+    return {
+        "ms_per_step": ms_step,
+        "glups": glups,
+        "kernel_ms": kernel_ms,
+        "kernel_gbs": bytes_per_site(storage) * n / (kernel_ms * 1e-3) / 1e9,
+        "u2_over_kT": float(u2.mean() * RHO0 / KT),
+        "u2_series": u2,
+        "nonfinite": float(st[:, 11].sum()),
+    }
+
+
+def cpu_baseline():
+    """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 40 steps
+    from rest (same parameters as the GPU workload)."""
+    import numpy as np  # noqa: F401
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    shape, steps = (64, 64, 64), 40
+    n = shape[0] * shape[1] * shape[2]
+    f = O.init_equilibrium(Q, n, rho0=RHO0)
+    t0 = time.perf_counter()
+    O.run(Q, shape, f, KT, O.paper_lambda(Q, 1 / TAU), SEED, 0, 0, steps, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"D3Q27 64^3 x {steps} steps from rest (rho0=1, tau=0.8, kT=1e-4, seed 1), "
+                      f"FP64 dense T(u) + LU, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--variants", default="f16,bf16")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup < 32:
+        args.warmup = 32  # the first graph capture happens inside the warm-up
+
+    import numpy as np
+    import torch
+    from paper_2602_16486_amd import _lib
+    if _lib.device_count() < 1 or not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()  # default priority
+    n = SHAPE[0] * SHAPE[1] * SHAPE[2]
+
+    log(f"timing f32: {args.warmup} warm-up + {args.steps} timed steps")
+    main_run = time_storage("f32", args.steps, args.warmup, stream, torch)
+    log(f"f32: {main_run['ms_per_step']:.4f} ms/step, {main_run['glups']:.2f} GLUPS")
+    variants = {}
+    for storage in [s for s in args.variants.split(",") if s]:
+        log(f"timing {storage}")
+        r = time_storage(storage, args.steps, args.warmup, stream, torch)
+        m = min(len(r["u2_series"]), len(main_run["u2_series"]))
+        du = float(np.abs(r["u2_series"][:m].mean() / main_run["u2_series"][:m].mean() - 1))
+        variants[storage] = {
+            "value": r["glups"], "ms_per_step": r["ms_per_step"],
+            "kernel_gbs": r["kernel_gbs"], "frac_hbm": r["kernel_gbs"] / PEAK_HBM_GBS,
+            "bytes_per_site": bytes_per_site(storage),
+            "u2_over_kT": r["u2_over_kT"], "u2_rel_diff_vs_f32": du,
+        }
+        log(f"{storage}: {r['glups']:.2f} GLUPS, <u2> rel diff vs f32 {du:.2e}")
+
+    achieved = main_run["kernel_gbs"]
+    result = {
+        "metric": "D3Q27 256^3 GLUPS (fused fluctuating CM step)",
+        "value": main_run["glups"],
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D3Q27 256^3 periodic, rest start, rho0=1, tau=0.8, kT=1e-4, Philox seed 1; "
+                        "FP32 deviation storage, FP32 collide, FP64 per-step statistics",
+            "lattice": "D3Q27", "box": list(SHAPE), "storage": "f32",
+            "bytes_per_site_step": bytes_per_site("f32"),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "kernel_ms": main_run["kernel_ms"],
+            "bytes_per_launch": bytes_per_site("f32") * n,
+        },
+        "u2_over_kT": main_run["u2_over_kT"],
+        "variants": variants,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle sample")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * cmflb.h -- C ABI of libcmflb, the MI355X (gfx950) implementation of the
+ * fused stream-and-collide step of the fluctuating orthogonal-central-moment
+ * lattice Boltzmann method (De Rosis & Zhou, "A fluctuating lattice
+ * Boltzmann formulation based on orthogonal central moments",
+ * arXiv 2602.16486), for the D2Q9 and D3Q27 lattices on periodic boxes.
+ *
+ * One time step is the paper's per-site algorithm (Sec. 2.2, "Algorithm of
+ * computation"): density and velocity (eq. macro), standard normals for the
+ * non-conserved modes, central moments k = T(u) f (Sec. 2.2/2.3), the
+ * collision k* = (I - Lambda) k + Lambda k_eq + I~ phi eta (eq. cm_collision)
+ * with phi from eq. phi_general, the back transformation f* = T(u)^-1 k*,
+ * and the streaming f_i(x + c_i, t + 1) = f*_i(x, t) (eq. streaming).
+ *
+ * Conventions shared by every entry point:
+ *  - Site order is x fastest: s = x + nx * (y + ny * z); nz = 1 for D2Q9.
+ *  - Population order is the paper's velocity order (Sec. 2.2 for D2Q9,
+ *    Sec. 2.3 for D3Q27).  "Populations" at the ABI are the pre-collision
+ *    populations f_i(x, t) of the current step t, in FP64, laid out q x N
+ *    (population-major).
+ *  - Noise: eta of mode v at site s and step t comes from Philox4x32-10
+ *    (Salmon et al., SC'11) with key (seed low word, seed high word) and
+ *    counter (s, t, replica, block); normal n = v - 3 (D2Q9) or v - 4 (D3Q27),
+ *    pair p = n / 2 uses block p / 2 and words 2 (p mod 2), 2 (p mod 2) + 1 as
+ *    (a, b); u1 = ((a >> 8) + 1) 2^-24, u2 = (b >> 8) 2^-24; the pair is
+ *    r cos(2 pi u2), r sin(2 pi u2) with r = sqrt(-2 ln u1) (even n takes the
+ *    cosine).  Results do not depend on tiling or launch shape.
+ *  - Every function returns CMF_OK (0) or a negative status; the message of
+ *    the last failure on the calling thread is cmf_last_error().  No
+ *    exception crosses the ABI.
+ *  - Host pointers are owned by the caller and are never retained.  Device
+ *    memory allocated by cmf_create is owned by the lattice and released by
+ *    cmf_destroy.
+ *  - Steps are enqueued asynchronously on the HIP stream given at creation
+ *    (NULL = the null stream); every call that returns host data
+ *    synchronises that stream first.
+ */
+#ifndef CMFLB_H
+#define CMFLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMF_OK 0
+#define CMF_EINVAL -1       /* invalid argument */
+#define CMF_ENOMEM -2       /* device or host allocation failed */
+#define CMF_EHIP -3         /* a HIP runtime call failed */
+#define CMF_ENONFINITE -4   /* a recorded step had non-finite rho or u */
+#define CMF_EUNSUPPORTED -5 /* combination not built into this library */
+
+/* Storage type of the populations in HBM.  Populations are stored as
+ * deviations f_i - w_i rho0.  F32/F16/BF16 collide in FP32; F64 collides in
+ * FP64.  F16/BF16 store (f_i - w_i rho0) / s_i with a per-population
+ * power-of-two scale s_i = 2^ceil(log2(sigma_i)),
+ * sigma_i = sqrt(rho0 kT w_i / c_s^2) (sigma_i = 1e-2 w_i when kT = 0),
+ * rounded to nearest even. */
+enum {
+  CMF_STORE_F64 = 0,
+  CMF_STORE_F32 = 1,
+  CMF_STORE_F16 = 2,
+  CMF_STORE_BF16 = 3
+};
+
+/* desc.flags */
+#define CMF_FLAG_NO_GRAPH 1u   /* enqueue launches directly, never capture */
+#define CMF_FLAG_NO_STATS 2u   /* skip the per-step statistics finalize */
+
+typedef struct {
+  int32_t q;         /* 9 (D2Q9) or 27 (D3Q27) */
+  int32_t nx, ny, nz;/* box edges, >= 1; nz must be 1 for D2Q9 */
+  int32_t storage;   /* CMF_STORE_* */
+  uint32_t flags;    /* CMF_FLAG_* */
+  double rho0;       /* reference density of the deviation storage, > 0 */
+  double tau;        /* relaxation time, omega = 1 / tau, tau >= 0.5 */
+  double kT;         /* thermal energy per site, >= 0 */
+  const double *lambda; /* NULL: the paper's rates (D2Q9: Lambda_4,5 = omega,
+                           others 1, Sec. 2.2; D3Q27: Lambda_7-9 = omega,
+                           others 1, Sec. 2.3).  Otherwise q host doubles,
+                           one rate per mode in [0, 2]; copied. */
+  uint64_t seed;     /* Philox key */
+  uint32_t replica;  /* third Philox counter word */
+  int32_t series_capacity; /* rows kept in the device statistics ring;
+                              0 selects 4096 */
+} cmf_desc;
+
+/* One row of the per-step statistics, taken from the pre-collision state
+ * of step `step` (the state whose density and velocity the collision of
+ * that step uses).  Sums run over all N sites and are accumulated in FP64. */
+typedef struct {
+  double step;      /* step index */
+  double sum_rho;   /* sum of rho */
+  double sum_j[3];  /* sum of rho u_a */
+  double sum_u[3];  /* sum of u_a */
+  double sum_u2[3]; /* sum of u_a^2 */
+  double nonfinite; /* number of sites whose rho or u is not finite */
+} cmf_moments;
+
+typedef struct cmf_lattice cmf_lattice;
+
+/* Version string of the library.  Never fails. */
+const char *cmf_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *cmf_last_error(void);
+
+/* Number of HIP devices visible (0 when there is none); never fails. */
+int cmf_device_count(void);
+
+/* Create a lattice on the current HIP device: validates `desc`, builds the
+ * per-mode constants in FP64 (norms b_v, rates Lambda_v, noise prefactors
+ * sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2) of eq. phi_general, storage
+ * scales) and allocates two population buffers of q x N elements of the
+ * storage type plus statistics scratch.  The populations start at rest
+ * (f = w rho0) at step 0.  `hip_stream` is a hipStream_t or NULL.
+ * Errors: CMF_EINVAL (bad sizes, tau < 0.5, kT < 0, rho0 <= 0, rates out of
+ * [0, 2], N >= 2^31), CMF_ENOMEM, CMF_EHIP. */
+int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
+
+/* Release all device memory of the lattice (synchronises its stream). */
+int cmf_destroy(cmf_lattice *lat);
+
+/* Set the state to the equilibrium f_eq(rho, u) of eq. feq (maximal Hermite
+ * order; Sec. 2.2, 2.3) and reset the step counter and statistics.
+ * rho: N host doubles or NULL (rho0 everywhere); u: 3 x N host doubles
+ * (u_x of all sites, then u_y, then u_z) or NULL (rest).  Synchronous. */
+int cmf_init_equilibrium(cmf_lattice *lat, const double *rho, const double *u);
+
+/* Overwrite the pre-collision populations f_i(x, t) of the current step with
+ * q x N host doubles (canonical layout).  The step counter is unchanged.
+ * Synchronous. */
+int cmf_set_populations(cmf_lattice *lat, const double *f);
+
+/* Copy the pre-collision populations f_i(x, t) of the current step into
+ * q x N host doubles (canonical layout).  Synchronous. */
+int cmf_get_populations(cmf_lattice *lat, double *f);
+
+/* Pre-collision populations of the current step at `n` sites: out[k*q + i]
+ * = f_i(sites[k]).  Site indices must lie in [0, N).  Synchronous. */
+int cmf_gather_sites(cmf_lattice *lat, const int64_t *sites, int64_t n,
+                     double *out);
+
+/* Enqueue `nsteps` fused steps (plus the statistics finalize of each step
+ * unless CMF_FLAG_NO_STATS) on the lattice's stream.  Runs of steps are
+ * replayed from captured HIP graphs unless CMF_FLAG_NO_GRAPH.
+ * Asynchronous; nsteps >= 0. */
+int cmf_step(cmf_lattice *lat, int64_t nsteps);
+
+/* Diagnostic timing: enqueue `nsteps` steps as direct launches (no graph)
+ * with a HIP event pair around every fused-step kernel on the lattice's
+ * stream, synchronise, and return in *kernel_ms the summed duration of the
+ * step kernels alone (statistics finalize excluded), in milliseconds.  The
+ * steps are real steps: the state and the statistics advance. */
+int cmf_profile_steps(cmf_lattice *lat, int64_t nsteps, double *kernel_ms);
+
+/* Wait for all work enqueued on the lattice's stream. */
+int cmf_synchronize(cmf_lattice *lat);
+
+/* Index of the next step to be computed (synchronises). */
+int cmf_get_step(cmf_lattice *lat, int64_t *step);
+
+/* Statistics rows of the steps completed since the previous call (or since
+ * init), oldest first, at most min(cap, series_capacity) of them (the most
+ * recent ones); *n_out receives the count.  Synchronises.  Returns
+ * CMF_ENONFINITE (after filling `out`) when one of the returned rows counts
+ * non-finite sites. */
+int cmf_stats(cmf_lattice *lat, cmf_moments *out, int64_t cap,
+              int64_t *n_out);
+
+/* Write the density and velocity of the current pre-collision state as
+ * FP32 into device buffers: rho_dev (N floats) and u_dev (3 x N floats,
+ * u_x block first).  Either pointer may be NULL.  Asynchronous on the
+ * lattice's stream. */
+int cmf_sample_macro(cmf_lattice *lat, void *rho_dev, void *u_dev);
+
+/* Diagnostic: the standard normals eta_v the step kernels draw, for the
+ * noisy modes of `n` consecutive sites starting at `site0` of step `step`.
+ * out: n x q host doubles, zero on the conserved modes.  `fp64` selects
+ * the FP64 transform (as in F64 storage) instead of the FP32 one.  Runs a
+ * device kernel on the null stream; synchronous. */
+int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step,
+                     int64_t site0, int64_t n, int32_t fp64, double *out);
+
+/* Diagnostic: Philox4x32-10 words for n counters (ctr[4k..4k+3]) under one
+ * key, computed on the device; out receives 4n words.  Synchronous. */
+int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0,
+                     uint32_t key1, uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMFLB_H */

@@ -1,0 +1,600 @@
+// cmflb_capi.hip -- implementation of the C ABI declared in include/cmflb.h:
+// lattice objects, the FP64 per-mode constants, launch geometry, captured
+// step graphs and the statistics ring.
+//
+// Method: De Rosis & Zhou, "A fluctuating lattice Boltzmann formulation based
+// on orthogonal central moments" (arXiv 2602.16486).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cmflb.h"
+#include "cmflb_device.h"
+#include "cmflb_internal.h"
+
+using namespace cmf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(call)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(CMF_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+constexpr int kGraphSteps = 32;
+
+// one-axis weights of the rest state: w(0) = 2/3, w(+-1) = 1/6; the D2Q9 and
+// D3Q27 weights of Sec. 2.2 / 2.3 are their products (4/9, 1/9, 1/36 and
+// 8/27, 2/27, 1/54, 1/216).
+double axis_weight(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+// one-axis norms sum_c w(c) P_p(c)^2 of P_0 = 1, P_1 = c, P_2 = c^2 - c_s^2
+const double kAxisNorm[3] = {1.0, 1.0 / 3.0, 2.0 / 9.0};
+
+template <class L>
+void lattice_weights(double *w) {
+  for (int i = 0; i < L::Q; ++i)
+    w[i] = axis_weight(L::cx[i]) * axis_weight(L::cy[i]) *
+           (L::D == 3 ? axis_weight(L::cz[i]) : 1.0);
+}
+
+// b_v of the paper's orthogonal bases (Sec. 2.2 and 2.3): products of the
+// one-axis norms; D2Q9 rows 3 and 4 are sums/differences of two orthogonal
+// products and have norm 2/9 + 2/9.
+void mode_norms(int q, double *b) {
+  if (q == 27) {
+    for (int v = 0; v < 27; ++v) {
+      const int pos = D3Q27::mode_pos[v];
+      b[v] = kAxisNorm[pos % 3] * kAxisNorm[(pos / 3) % 3] * kAxisNorm[pos / 9];
+    }
+  } else {
+    const int px[9] = {0, 1, 0, -1, -1, 1, 2, 1, 2};
+    const int py[9] = {0, 0, 1, -1, -1, 1, 1, 2, 2};
+    for (int v = 0; v < 9; ++v)
+      b[v] = px[v] < 0 ? 2.0 * kAxisNorm[2] * kAxisNorm[0]
+                       : kAxisNorm[px[v]] * kAxisNorm[py[v]];
+  }
+}
+
+bool is_omega_mode(int q, int v) {
+  return q == 9 ? (v == 4 || v == 5) : (v >= 7 && v <= 9);
+}
+
+int first_noisy(int q) { return q == 9 ? 3 : 4; }
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case kF64: return 8;
+    case kF32: return 4;
+    case kF16:
+    case kBF16: return 2;
+  }
+  return 0;
+}
+
+int env_int(const char *name, int dflt) {
+  const char *s = getenv(name);
+  if (!s || !*s) return dflt;
+  return atoi(s);
+}
+
+}  // namespace
+
+struct cmf_lattice {
+  cmf_desc desc;
+  int q = 0;
+  int storage = 0;
+  bool general = false;
+  bool own_stream = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t N = 0;
+  int64_t pstride = 0;
+  void *buf[2] = {nullptr, nullptr};
+  int parity = 0;  // buf[parity] holds the state of the current step
+  double *partials = nullptr;
+  int nparts = 0;
+  double *series = nullptr;
+  int cap = 0;
+  int64_t *step_dev = nullptr;
+  int64_t read_step = 0;   // first step whose statistics were not returned
+  int64_t host_step = 0;   // steps enqueued so far
+  int block = 256;
+  int grid = 1;
+  double lambda[27];
+  double w[27];
+  double mass0 = 0.0;
+  StepParams<float> pf;
+  StepParams<double> pd;
+  ConvParams cp;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+template <typename R>
+void fill_step_params(const cmf_lattice *L, const double *amp,
+                      const float *scale, StepParams<R> &p) {
+  memset(&p, 0, sizeof p);
+  p.nx = L->desc.nx;
+  p.ny = L->desc.ny;
+  p.nz = L->desc.nz;
+  p.nxb = (L->desc.nx + L->block - 1) / L->block;
+  p.ntiles = p.nxb * p.ny * p.nz;
+  p.noise = L->desc.kT > 0.0 ? 1 : 0;
+  p.pstride = L->pstride;
+  p.rho0 = (R)L->desc.rho0;
+  for (int v = 0; v < L->q; ++v) {
+    p.amp[v] = (R)amp[v];
+    p.oml[v] = (R)(1.0 - L->lambda[v]);
+    p.lam[v] = (R)L->lambda[v];
+  }
+  for (int i = 0; i < L->q; ++i) {
+    p.scale[i] = scale[i];
+    p.iscale[i] = 1.0f / scale[i];
+  }
+  p.key0 = (uint32_t)L->desc.seed;
+  p.key1 = (uint32_t)(L->desc.seed >> 32);
+  p.replica = L->desc.replica;
+}
+
+const void *step_params(const cmf_lattice *L) {
+  return L->storage == kF64 ? (const void *)&L->pd : (const void *)&L->pf;
+}
+
+int enqueue_one_step(cmf_lattice *L) {
+  const void *src = L->buf[L->parity];
+  void *dst = L->buf[1 - L->parity];
+  HIP_TRY(launch_step(L->q, L->storage, L->general, step_params(L), src, dst,
+                      L->step_dev, L->partials, L->grid, L->block, L->stream));
+  HIP_TRY(launch_finalize(L->partials, L->nparts, L->series, L->cap,
+                          L->step_dev, L->mass0,
+                          !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream));
+  L->parity ^= 1;
+  return CMF_OK;
+}
+
+int capture_graph(cmf_lattice *L, int parity) {
+  const int saved = L->parity;
+  L->parity = parity;
+  HIP_TRY(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
+  int rc = CMF_OK;
+  for (int s = 0; s < kGraphSteps && rc == CMF_OK; ++s) rc = enqueue_one_step(L);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(L->stream, &g);
+  L->parity = saved;
+  if (rc != CMF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess)
+    return fail(CMF_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&L->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess)
+    return fail(CMF_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+void release(cmf_lattice *L) {
+  if (!L) return;
+  if (L->stream) (void)hipStreamSynchronize(L->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (L->graph[k]) (void)hipGraphExecDestroy(L->graph[k]);
+    if (L->buf[k]) (void)hipFree(L->buf[k]);
+  }
+  if (L->partials) (void)hipFree(L->partials);
+  if (L->series) (void)hipFree(L->series);
+  if (L->step_dev) (void)hipFree(L->step_dev);
+  if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+  delete L;
+}
+
+int validate(const cmf_desc *d) {
+  if (!d) return fail(CMF_EINVAL, "desc is NULL");
+  if (d->q != 9 && d->q != 27) return fail(CMF_EINVAL, "q must be 9 or 27, got %d", d->q);
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+    return fail(CMF_EINVAL, "box edges must be >= 1 (%d, %d, %d)", d->nx, d->ny, d->nz);
+  if (d->q == 9 && d->nz != 1) return fail(CMF_EINVAL, "D2Q9 needs nz = 1, got %d", d->nz);
+  const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+  if (N >= (int64_t)1 << 31) return fail(CMF_EINVAL, "N = %lld sites exceeds 2^31 - 1", (long long)N);
+  if (d->storage < kF64 || d->storage > kBF16) return fail(CMF_EINVAL, "unknown storage %d", d->storage);
+  if (!(d->rho0 > 0.0) || !isfinite(d->rho0)) return fail(CMF_EINVAL, "rho0 must be > 0");
+  if (!(d->tau >= 0.5) || !isfinite(d->tau)) return fail(CMF_EINVAL, "tau must be >= 0.5");
+  if (!(d->kT >= 0.0) || !isfinite(d->kT)) return fail(CMF_EINVAL, "kT must be >= 0");
+  if (d->lambda)
+    for (int v = 0; v < d->q; ++v)
+      if (!(d->lambda[v] >= 0.0 && d->lambda[v] <= 2.0))
+        return fail(CMF_EINVAL, "lambda[%d] = %g outside [0, 2]", v, d->lambda[v]);
+  if (d->series_capacity < 0) return fail(CMF_EINVAL, "series_capacity < 0");
+  return CMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cmf_version(void) { return "cmflb 0.1 (gfx950)"; }
+
+const char *cmf_last_error(void) { return g_last_error.c_str(); }
+
+int cmf_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
+  if (!out) return fail(CMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc != CMF_OK) return rc;
+  cmf_lattice *L = new cmf_lattice();
+  L->desc = *desc;
+  L->desc.lambda = nullptr;
+  L->q = desc->q;
+  L->storage = desc->storage;
+  L->N = (int64_t)desc->nx * desc->ny * desc->nz;
+  L->pstride = (L->N + 127) / 128 * 128;
+  L->cap = desc->series_capacity > 0 ? desc->series_capacity : 4096;
+  const int q = L->q;
+
+  // rates: the paper's pattern unless given
+  const double omega = 1.0 / desc->tau;
+  for (int v = 0; v < q; ++v)
+    L->lambda[v] = desc->lambda ? desc->lambda[v] : (is_omega_mode(q, v) ? omega : 1.0);
+  L->general = false;
+  for (int v = first_noisy(q); v < q; ++v)
+    if (!is_omega_mode(q, v) && L->lambda[v] != 1.0) L->general = true;
+  if (env_int("CMF_FORCE_GENERAL", 0)) L->general = true;
+
+  // FP64 constants: weights, norms, noise amplitudes (eq. phi_general
+  // without the local sqrt(rho)), storage scales
+  double b[27], amp[27];
+  float scale[27];
+  if (q == 9) lattice_weights<D2Q9>(L->w); else lattice_weights<D3Q27>(L->w);
+  mode_norms(q, b);
+  for (int v = 0; v < q; ++v) {
+    const double lv = L->lambda[v];
+    amp[v] = v >= first_noisy(q) ? sqrt(desc->kT * lv * (2.0 - lv) * b[v] / kCs2) : 0.0;
+  }
+  for (int i = 0; i < q; ++i) {
+    if (L->storage == kF16 || L->storage == kBF16) {
+      double sigma = desc->kT > 0.0 ? sqrt(desc->rho0 * desc->kT * L->w[i] / kCs2)
+                                    : 1e-2 * L->w[i];
+      scale[i] = (float)ldexp(1.0, (int)ceil(log2(sigma)));
+    } else {
+      scale[i] = 1.0f;
+    }
+  }
+  L->mass0 = (double)L->N * desc->rho0;
+
+  // launch geometry: tiles of BX sites along x, persistent-style grid
+  const int bx_env = env_int("CMF_BLOCK", 0);
+  int bx = desc->nx >= 192 ? 256 : ((desc->nx + 63) / 64) * 64;
+  if (bx_env == 64 || bx_env == 128 || bx_env == 192 || bx_env == 256) bx = bx_env;
+  L->block = bx;
+  fill_step_params(L, amp, scale, L->pd);
+  fill_step_params(L, amp, scale, L->pf);
+  const int ntiles = L->pf.ntiles;
+  int grid = env_int("CMF_GRID", 0);
+  if (grid <= 0) grid = 2048;
+  L->grid = grid < ntiles ? grid : ntiles;
+  L->nparts = L->grid;
+
+  L->cp.nx = desc->nx;
+  L->cp.ny = desc->ny;
+  L->cp.nz = desc->nz;
+  L->cp.pstride = L->pstride;
+  L->cp.rho0 = desc->rho0;
+  for (int i = 0; i < q; ++i) {
+    L->cp.w[i] = L->w[i];
+    L->cp.scale[i] = scale[i];
+    L->cp.iscale[i] = 1.0f / scale[i];
+  }
+
+  hipError_t e = hipGetDevice(&L->device);
+  if (e != hipSuccess) {
+    release(L);
+    return fail(CMF_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  }
+  if (hip_stream) {
+    L->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreate(&L->stream);
+    if (e != hipSuccess) {
+      release(L);
+      return fail(CMF_EHIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    L->own_stream = true;
+  }
+  const size_t bytes = (size_t)q * L->pstride * storage_bytes(L->storage);
+  for (int k = 0; k < 2; ++k) {
+    if (hipMalloc(&L->buf[k], bytes) != hipSuccess) {
+      release(L);
+      return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+  }
+  if (hipMalloc((void **)&L->partials, sizeof(double) * kPartStride * L->nparts) != hipSuccess ||
+      hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
+      hipMalloc((void **)&L->step_dev, sizeof(int64_t)) != hipSuccess) {
+    release(L);
+    return fail(CMF_ENOMEM, "hipMalloc of statistics buffers failed");
+  }
+  *out = L;
+  rc = cmf_init_equilibrium(L, nullptr, nullptr);
+  if (rc != CMF_OK) {
+    release(L);
+    *out = nullptr;
+    return rc;
+  }
+  return CMF_OK;
+}
+
+int cmf_destroy(cmf_lattice *L) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  release(L);
+  return CMF_OK;
+}
+
+int cmf_init_equilibrium(cmf_lattice *L, const double *rho, const double *u) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  double *drho = nullptr, *du = nullptr;
+  const int64_t N = L->N;
+  if (rho) {
+    for (int64_t s = 0; s < N; ++s)
+      if (!(rho[s] > 0.0) || !isfinite(rho[s]))
+        return fail(CMF_EINVAL, "rho[%lld] = %g is not a positive density", (long long)s, rho[s]);
+    HIP_TRY(hipMalloc((void **)&drho, sizeof(double) * N));
+    HIP_TRY(hipMemcpy(drho, rho, sizeof(double) * N, hipMemcpyHostToDevice));
+  }
+  if (u) {
+    if (hipMalloc((void **)&du, sizeof(double) * 3 * N) != hipSuccess) {
+      if (drho) (void)hipFree(drho);
+      return fail(CMF_ENOMEM, "hipMalloc of the velocity field failed");
+    }
+    HIP_TRY(hipMemcpy(du, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
+  }
+  L->parity = 0;
+  hipError_t e = launch_init_eq(L->q, L->storage, L->cp, drho, du, L->buf[0], L->stream);
+  if (e == hipSuccess) e = launch_zero_i64(L->step_dev, 1, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (drho) (void)hipFree(drho);
+  if (du) (void)hipFree(du);
+  if (e != hipSuccess) return fail(CMF_EHIP, "equilibrium initialisation failed: %s", hipGetErrorString(e));
+  L->read_step = 0;
+  L->host_step = 0;
+  return CMF_OK;
+}
+
+int cmf_set_populations(cmf_lattice *L, const double *f) {
+  if (!L || !f) return fail(CMF_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  double *df = nullptr;
+  const size_t bytes = sizeof(double) * L->q * L->N;
+  if (hipMalloc((void **)&df, bytes) != hipSuccess)
+    return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  hipError_t e = hipMemcpy(df, f, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_set_state(L->q, L->storage, L->cp, df, L->buf[L->parity], L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(df);
+  if (e != hipSuccess) return fail(CMF_EHIP, "set_populations failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_get_populations(cmf_lattice *L, double *f) {
+  if (!L || !f) return fail(CMF_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  double *df = nullptr;
+  const size_t bytes = sizeof(double) * L->q * L->N;
+  if (hipMalloc((void **)&df, bytes) != hipSuccess)
+    return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  hipError_t e = launch_get_state(L->q, L->storage, L->cp, L->buf[L->parity], df, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e == hipSuccess) e = hipMemcpy(f, df, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(df);
+  if (e != hipSuccess) return fail(CMF_EHIP, "get_populations failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_gather_sites(cmf_lattice *L, const int64_t *sites, int64_t n, double *out) {
+  if (!L || (n > 0 && (!sites || !out))) return fail(CMF_EINVAL, "NULL argument");
+  if (n < 0) return fail(CMF_EINVAL, "n < 0");
+  if (n == 0) return CMF_OK;
+  for (int64_t k = 0; k < n; ++k)
+    if (sites[k] < 0 || sites[k] >= L->N)
+      return fail(CMF_EINVAL, "site %lld outside [0, %lld)", (long long)sites[k], (long long)L->N);
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  int64_t *ds = nullptr;
+  double *dout = nullptr;
+  if (hipMalloc((void **)&ds, sizeof(int64_t) * n) != hipSuccess ||
+      hipMalloc((void **)&dout, sizeof(double) * L->q * n) != hipSuccess) {
+    if (ds) (void)hipFree(ds);
+    return fail(CMF_ENOMEM, "hipMalloc failed");
+  }
+  hipError_t e = hipMemcpy(ds, sites, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_gather(L->q, L->storage, L->cp, L->buf[L->parity], ds, n, dout, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(double) * L->q * n, hipMemcpyDeviceToHost);
+  (void)hipFree(ds);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return fail(CMF_EHIP, "gather_sites failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_step(cmf_lattice *L, int64_t nsteps) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (nsteps < 0) return fail(CMF_EINVAL, "nsteps < 0");
+  const bool graphs = !(L->desc.flags & CMF_FLAG_NO_GRAPH);
+  int64_t left = nsteps;
+  while (graphs && left >= kGraphSteps) {
+    if (!L->graph[L->parity]) {
+      int rc = capture_graph(L, L->parity);
+      if (rc != CMF_OK) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(L->graph[L->parity], L->stream));
+    left -= kGraphSteps;  // an even number of steps: parity unchanged
+  }
+  for (; left > 0; --left) {
+    int rc = enqueue_one_step(L);
+    if (rc != CMF_OK) return rc;
+  }
+  L->host_step += nsteps;
+  return CMF_OK;
+}
+
+int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
+  if (!L || !kernel_ms) return fail(CMF_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CMF_EINVAL, "nsteps < 0");
+  *kernel_ms = 0.0;
+  if (nsteps == 0) return CMF_OK;
+  std::vector<hipEvent_t> ev(2 * nsteps, nullptr);
+  for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+  int rc = CMF_OK;
+  for (int64_t s = 0; s < nsteps && rc == CMF_OK; ++s) {
+    const void *src = L->buf[L->parity];
+    void *dst = L->buf[1 - L->parity];
+    hipError_t e = hipEventRecord(ev[2 * s], L->stream);
+    if (e == hipSuccess)
+      e = launch_step(L->q, L->storage, L->general, step_params(L), src, dst, L->step_dev,
+                      L->partials, L->grid, L->block, L->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
+    if (e == hipSuccess)
+      e = launch_finalize(L->partials, L->nparts, L->series, L->cap, L->step_dev, L->mass0,
+                          !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream);
+    if (e != hipSuccess) rc = fail(CMF_EHIP, "profiled step failed: %s", hipGetErrorString(e));
+    L->parity ^= 1;
+  }
+  hipError_t e = hipStreamSynchronize(L->stream);
+  if (rc == CMF_OK && e != hipSuccess) rc = fail(CMF_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+  double total = 0.0;
+  for (int64_t s = 0; s < nsteps && rc == CMF_OK; ++s) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
+    if (e != hipSuccess) rc = fail(CMF_EHIP, "hipEventElapsedTime failed: %s", hipGetErrorString(e));
+    total += ms;
+  }
+  for (auto &x : ev) (void)hipEventDestroy(x);
+  L->host_step += nsteps;
+  *kernel_ms = total;
+  return rc;
+}
+
+int cmf_synchronize(cmf_lattice *L) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  return CMF_OK;
+}
+
+int cmf_get_step(cmf_lattice *L, int64_t *step) {
+  if (!L || !step) return fail(CMF_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  HIP_TRY(hipMemcpy(step, L->step_dev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return CMF_OK;
+}
+
+int cmf_stats(cmf_lattice *L, cmf_moments *out, int64_t cap, int64_t *n_out) {
+  if (!L || !n_out || (cap > 0 && !out)) return fail(CMF_EINVAL, "NULL argument");
+  *n_out = 0;
+  int64_t step = 0;
+  int rc = cmf_get_step(L, &step);
+  if (rc != CMF_OK) return rc;
+  if (L->desc.flags & CMF_FLAG_NO_STATS) {
+    L->read_step = step;
+    return CMF_OK;
+  }
+  int64_t first = L->read_step;
+  if (step - first > L->cap) first = step - L->cap;
+  if (step - first > cap) first = step - cap;
+  std::vector<double> ring((size_t)L->cap * kSeriesStride);
+  if (step > first)
+    HIP_TRY(hipMemcpy(ring.data(), L->series, sizeof(double) * ring.size(),
+                      hipMemcpyDeviceToHost));
+  std::vector<double> rows((size_t)(step - first) * kSeriesStride);
+  for (int64_t s = first; s < step; ++s)
+    memcpy(rows.data() + (s - first) * kSeriesStride,
+           ring.data() + (s % L->cap) * kSeriesStride, sizeof(double) * kSeriesStride);
+  bool bad = false;
+  for (int64_t s = first; s < step; ++s) {
+    const double *r = rows.data() + (s - first) * kSeriesStride;
+    cmf_moments &m = out[s - first];
+    m.step = r[0];
+    m.sum_rho = r[1];
+    for (int a = 0; a < 3; ++a) {
+      m.sum_j[a] = r[2 + a];
+      m.sum_u[a] = r[5 + a];
+      m.sum_u2[a] = r[8 + a];
+    }
+    m.nonfinite = r[11];
+    if (m.nonfinite != 0.0) bad = true;
+  }
+  *n_out = step - first;
+  L->read_step = step;
+  if (bad) return fail(CMF_ENONFINITE, "non-finite density or velocity in a recorded step");
+  return CMF_OK;
+}
+
+int cmf_sample_macro(cmf_lattice *L, void *rho_dev, void *u_dev) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  HIP_TRY(launch_macro(L->q, L->storage, L->cp, L->buf[L->parity], (float *)rho_dev,
+                       (float *)u_dev, L->stream));
+  return CMF_OK;
+}
+
+int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step, int64_t site0,
+                     int64_t n, int32_t fp64, double *out) {
+  if (q != 9 && q != 27) return fail(CMF_EINVAL, "q must be 9 or 27");
+  if (n < 0 || site0 < 0 || site0 + n > ((int64_t)1 << 32)) return fail(CMF_EINVAL, "bad site range");
+  if (n == 0) return CMF_OK;
+  if (!out) return fail(CMF_EINVAL, "out is NULL");
+  double *d = nullptr;
+  if (hipMalloc((void **)&d, sizeof(double) * q * n) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc failed");
+  hipError_t e = launch_noise(q, fp64, (uint32_t)seed, (uint32_t)(seed >> 32), replica, step, site0, n, d,
+                              nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, d, sizeof(double) * q * n, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(CMF_EHIP, "noise_sample failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t *out) {
+  if (n < 0) return fail(CMF_EINVAL, "n < 0");
+  if (n == 0) return CMF_OK;
+  if (!ctr || !out) return fail(CMF_EINVAL, "NULL argument");
+  uint32_t *dc = nullptr, *dout = nullptr;
+  if (hipMalloc((void **)&dc, 16 * n) != hipSuccess || hipMalloc((void **)&dout, 16 * n) != hipSuccess) {
+    if (dc) (void)hipFree(dc);
+    return fail(CMF_ENOMEM, "hipMalloc failed");
+  }
+  hipError_t e = hipMemcpy(dc, ctr, 16 * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_philox(dc, n, key0, key1, dout, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, dout, 16 * n, hipMemcpyDeviceToHost);
+  (void)hipFree(dc);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return fail(CMF_EHIP, "philox_words failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+}  // extern "C"

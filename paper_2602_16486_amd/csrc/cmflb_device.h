@@ -1,0 +1,325 @@
+// cmflb_device.h -- device building blocks of the fused CM-FLBM step for
+// gfx950: lattice traits, Philox4x32-10 + Box-Muller normals, storage
+// conversions, and the per-site collision written as tensor-product passes.
+//
+// Method: De Rosis & Zhou, "A fluctuating lattice Boltzmann formulation based
+// on orthogonal central moments" (arXiv 2602.16486).
+//
+// Factorisation used here (a property of the paper's bases, not a step the
+// paper prints): every D3Q27 basis row of Sec. 2.3 is a product
+// P_px(c_x) P_py(c_y) P_pz(c_z) of the one-dimensional polynomials
+// P_0 = 1, P_1 = c, P_2 = c^2 - c_s^2 (row 15 read as (c_y^2 - c_s^2) c_z);
+// the D2Q9 basis of Sec. 2.2 is the same tensor basis in 2-D except that
+// rows 3 and 4 are P_2 P_0 + P_0 P_2 and P_2 P_0 - P_0 P_2.  Shifting c by u
+// keeps that structure, so T(u) = T1(u_x) (x) T1(u_y) (x) T1(u_z) and both
+// k = T(u) f and f* = T(u)^-1 k* are three (two) passes of 3x3 one-axis maps
+// instead of a dense 27x27 (9x9) product.
+//
+// Deviation form: the step stores d_i = f_i - w_i rho0.  With
+// g(u) = (1, -u, u^2) the one-axis central moments of the rest weights,
+// T(u) (rho0 w) = rho0 g(u_x) (x) g(u_y) (x) g(u_z), so
+//   k   = T(u) d + rho0 G(u)        and
+//   d*  = T(u)^-1 (k* - rho0 G(u)),
+// which keeps every intermediate O(fluctuation) in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace cmf {
+
+// ---------------------------------------------------------------------------
+// Lattices, in the paper's velocity order.
+// ---------------------------------------------------------------------------
+
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int D = 2;
+  static constexpr int NT = 9;          // tensor positions 3^D
+  static constexpr int FIRST_NOISY = 3; // I~ = diag[0,0,0,1,...] (Sec. 2.2)
+  static constexpr int NNOISE = 6;
+  static constexpr int NBLOCKS = 2;     // Philox blocks per site and step
+  // Sec. 2.2: c_x = [0,1,0,-1,0,1,-1,-1,1], c_y = [0,0,1,0,-1,1,1,-1,-1]
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+struct D3Q27 {
+  static constexpr int Q = 27;
+  static constexpr int D = 3;
+  static constexpr int NT = 27;
+  static constexpr int FIRST_NOISY = 4; // I~_0-3 = 0 (Sec. 2.3)
+  static constexpr int NNOISE = 23;
+  static constexpr int NBLOCKS = 6;
+  // Sec. 2.3, component lists of the 27 velocities
+  static constexpr int cx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1,
+                                 -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr int cy[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0,
+                                 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+  static constexpr int cz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1,
+                                 -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+  // tensor index px + 3 py + 9 pz of mode v (Sec. 2.3 rows as products of
+  // P_0, P_1, P_2 per axis)
+  static constexpr int mode_pos[27] = {
+      0,            // 1
+      1, 3, 9,      // c_x, c_y, c_z
+      2, 6, 18,     // P2(x), P2(y), P2(z)
+      4, 10, 12,    // xy, xz, yz
+      5, 11,        // P2(x) y, P2(x) z
+      7, 19,        // x P2(y), x P2(z)
+      21, 15,       // y P2(z), P2(y) z
+      13,           // xyz
+      8, 20, 24,    // P2 P2 0, P2 0 P2, 0 P2 P2
+      22, 16, 14,   // x y P2(z), x P2(y) z, P2(x) y z
+      23, 17, 25,   // P2 y P2, P2 P2 z, x P2 P2
+      26};          // P2 P2 P2
+};
+
+// tensor position (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1) of population i
+template <class L>
+__host__ __device__ constexpr int pop_pos(int i) {
+  return (L::cx[i] + 1) + 3 * (L::cy[i] + 1) + 9 * (L::cz[i] + 1);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round, the 64-bit
+// products of words 0 and 2 with 0xD2511F53 and 0xCD9E8D57 give the new
+// words (hi(2) ^ w1 ^ k0, lo(2), hi(0) ^ w3 ^ k1, lo(0)); the key advances by
+// (0x9E3779B9, 0xBB67AE85) between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1,
+                                            uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// Box-Muller pair from two Philox words (a -> radius, b -> angle).
+template <typename R>
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, R &z0,
+                                           R &z1);
+
+template <>
+__device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b,
+                                                  float &z0, float &z1) {
+  const float u1 = (float)((a >> 8) + 1u) * 0x1p-24f;  // (0, 1], exact
+  const float u2 = (float)(b >> 8) * 0x1p-24f;         // [0, 1), exact
+  const float r = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+template <>
+__device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b,
+                                                   double &z0, double &z1) {
+  const double u1 = (double)((a >> 8) + 1u) * 0x1p-24;
+  const double u2 = (double)(b >> 8) * 0x1p-24;
+  const double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// The NNOISE normals of one site and step, eta[n] for mode FIRST_NOISY + n.
+template <class L, typename R>
+__device__ __forceinline__ void site_normals(uint32_t site, uint32_t step,
+                                             uint32_t replica, uint32_t k0,
+                                             uint32_t k1, R *eta) {
+#pragma unroll
+  for (int blk = 0; blk < L::NBLOCKS; ++blk) {
+    const U4 w = philox4x32_10(site, step, replica, (uint32_t)blk, k0, k1);
+    const int n0 = 4 * blk;
+    R a, b;
+    box_muller<R>(w.x, w.y, a, b);
+    if (n0 < L::NNOISE) eta[n0] = a;
+    if (n0 + 1 < L::NNOISE) eta[n0 + 1] = b;
+    if (n0 + 2 < L::NNOISE) {
+      R c, d;
+      box_muller<R>(w.z, w.w, c, d);
+      eta[n0 + 2] = c;
+      if (n0 + 3 < L::NNOISE) eta[n0 + 3] = d;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-axis maps between populations (c = -1, 0, +1) and central moments
+// (P_0, P_1, P_2 of c - u), in place.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Axis {
+  R u, twou, u2mcs2, cs2pu2;
+  __device__ __forceinline__ explicit Axis(R uu) {
+    const R cs2 = R(1) / R(3);
+    u = uu;
+    twou = uu + uu;
+    u2mcs2 = uu * uu - cs2;
+    cs2pu2 = uu * uu + cs2;
+  }
+  // (g-, g0, g+) -> (m0, m1, m2)
+  __device__ __forceinline__ void fwd(R &a0, R &a1, R &a2) const {
+    const R m0 = a0 + a1 + a2;
+    const R d = a2 - a0;
+    const R s = a2 + a0;
+    a0 = m0;
+    a1 = d - u * m0;
+    a2 = s - twou * d + u2mcs2 * m0;
+  }
+  // (m0, m1, m2) -> (g-, g0, g+)
+  __device__ __forceinline__ void inv(R &a0, R &a1, R &a2) const {
+    const R r1 = a1 + u * a0;
+    const R r2 = a2 + cs2pu2 * a0 + twou * a1;
+    const R g0 = a0 - r2;
+    a0 = R(0.5) * (r2 - r1);
+    a1 = g0;
+    a2 = R(0.5) * (r2 + r1);
+  }
+};
+
+// passes over a 3^D tensor t[px + 3 py + 9 pz]
+template <int D, typename R>
+__device__ __forceinline__ void tensor_fwd(R *t, const Axis<R> &ax,
+                                           const Axis<R> &ay,
+                                           const Axis<R> &az) {
+  constexpr int NZ = D == 3 ? 3 : 1;
+#pragma unroll
+  for (int k = 0; k < 3 * NZ; ++k) ax.fwd(t[3 * k], t[3 * k + 1], t[3 * k + 2]);
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+      ay.fwd(t[x + 9 * z], t[x + 3 + 9 * z], t[x + 6 + 9 * z]);
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) az.fwd(t[k], t[k + 9], t[k + 18]);
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void tensor_inv(R *t, const Axis<R> &ax,
+                                           const Axis<R> &ay,
+                                           const Axis<R> &az) {
+  constexpr int NZ = D == 3 ? 3 : 1;
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) az.inv(t[k], t[k + 9], t[k + 18]);
+  }
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+      ay.inv(t[x + 9 * z], t[x + 3 + 9 * z], t[x + 6 + 9 * z]);
+#pragma unroll
+  for (int k = 0; k < 3 * NZ; ++k) ax.inv(t[3 * k], t[3 * k + 1], t[3 * k + 2]);
+}
+
+// t[p] += s * G(u)[p], G = g(u_x) (x) g(u_y) (x) g(u_z), g(u) = (1, -u, u^2)
+template <int D, typename R>
+__device__ __forceinline__ void add_rest_moments(R *t, R s, R ux, R uy, R uz) {
+  const R gx[3] = {s, -s * ux, s * ux * ux};
+  const R gy[3] = {R(1), -uy, uy * uy};
+  if constexpr (D == 3) {
+    const R gz[3] = {R(1), -uz, uz * uz};
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+      for (int y = 0; y < 3; ++y) {
+        const R gyz = gy[y] * gz[z];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) t[x + 3 * y + 9 * z] += gx[x] * gyz;
+      }
+  } else {
+    (void)uz;
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int x = 0; x < 3; ++x) t[x + 3 * y] += gx[x] * gy[y];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Storage conversions.  F16/BF16 hold d_i / s_i (s_i a power of two).
+// ---------------------------------------------------------------------------
+template <typename S, typename R>
+struct Store;
+
+template <typename R>
+struct Store<double, R> {
+  static constexpr bool scaled = false;
+  __device__ __forceinline__ static R load(const double *p, float) {
+    return (R)__builtin_nontemporal_load(p);
+  }
+  __device__ __forceinline__ static void store(double *p, R v, float) {
+    __builtin_nontemporal_store((double)v, p);
+  }
+};
+
+template <typename R>
+struct Store<float, R> {
+  static constexpr bool scaled = false;
+  __device__ __forceinline__ static R load(const float *p, float) {
+    return (R)__builtin_nontemporal_load(p);
+  }
+  __device__ __forceinline__ static void store(float *p, R v, float) {
+    __builtin_nontemporal_store((float)v, p);
+  }
+};
+
+template <typename R>
+struct Store<__half, R> {
+  static constexpr bool scaled = true;
+  __device__ __forceinline__ static R load(const __half *p, float scale) {
+    const unsigned short bits =
+        __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+    return (R)(__half2float(__ushort_as_half(bits)) * scale);
+  }
+  __device__ __forceinline__ static void store(__half *p, R v, float iscale) {
+    const __half h = __float2half_rn((float)v * iscale);
+    __builtin_nontemporal_store(__half_as_ushort(h),
+                                reinterpret_cast<unsigned short *>(p));
+  }
+};
+
+template <typename R>
+struct Store<__hip_bfloat16, R> {
+  static constexpr bool scaled = true;
+  __device__ __forceinline__ static R load(const __hip_bfloat16 *p,
+                                           float scale) {
+    const unsigned short bits =
+        __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+    return (R)(__uint_as_float(((unsigned int)bits) << 16) * scale);
+  }
+  __device__ __forceinline__ static void store(__hip_bfloat16 *p, R v,
+                                               float iscale) {
+    const __hip_bfloat16 h = __float2bfloat16((float)v * iscale);
+    unsigned short bits;
+    __builtin_memcpy(&bits, &h, sizeof(bits));
+    __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short *>(p));
+  }
+};
+
+}  // namespace cmf

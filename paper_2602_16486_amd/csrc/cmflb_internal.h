@@ -1,0 +1,70 @@
+// cmflb_internal.h -- declarations shared by the kernel translation unit and
+// the C-ABI implementation of libcmflb (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmf {
+
+constexpr int kNAcc = 11;      // accumulated statistics per block
+constexpr int kPartStride = 12;// doubles per block partial
+constexpr int kSeriesStride = 12;
+constexpr int kMaxBlock = 256;
+
+// Parameters of one lattice as the step kernels see them (kernel argument,
+// so every field lives in scalar registers).
+template <typename R>
+struct StepParams {
+  int32_t nx, ny, nz, nxb;  // box and x-tiles per row
+  int32_t ntiles;           // nxb * ny * nz
+  int32_t noise;            // kT > 0
+  int64_t pstride;          // elements between population planes
+  R rho0;
+  R amp[27];   // I~_v sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2)
+  R oml[27];   // 1 - Lambda_v
+  R lam[27];   // Lambda_v
+  float scale[27], iscale[27];  // storage scale s_i and 1 / s_i
+  uint32_t key0, key1, replica;
+};
+
+// Parameters of the state conversion kernels (FP64 always).
+struct ConvParams {
+  int32_t nx, ny, nz;
+  int64_t pstride;
+  double rho0;
+  double w[27];
+  float scale[27], iscale[27];
+};
+
+enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+// launchers (defined in cmflb_kernels.hip); all return hipError_t
+hipError_t launch_step(int q, int storage, bool general, const void *params,
+                       const void *src, void *dst, const int64_t *step_ptr,
+                       double *partials, int grid, int block,
+                       hipStream_t stream);
+hipError_t launch_finalize(const double *partials, int nparts, double *series,
+                           int cap, int64_t *step_ptr, double mass0,
+                           bool stats, hipStream_t stream);
+hipError_t launch_init_eq(int q, int storage, const ConvParams &cp,
+                          const double *rho, const double *u, void *buf,
+                          hipStream_t stream);
+hipError_t launch_set_state(int q, int storage, const ConvParams &cp,
+                            const double *f, void *buf, hipStream_t stream);
+hipError_t launch_get_state(int q, int storage, const ConvParams &cp,
+                            const void *buf, double *f, hipStream_t stream);
+hipError_t launch_gather(int q, int storage, const ConvParams &cp,
+                         const void *buf, const int64_t *sites, int64_t n,
+                         double *out, hipStream_t stream);
+hipError_t launch_macro(int q, int storage, const ConvParams &cp,
+                        const void *buf, float *rho, float *u,
+                        hipStream_t stream);
+hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
+                        uint32_t replica, uint32_t step, int64_t site0,
+                        int64_t n, double *out, hipStream_t stream);
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
+                         uint32_t key1, uint32_t *out, hipStream_t stream);
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
+
+}  // namespace cmf

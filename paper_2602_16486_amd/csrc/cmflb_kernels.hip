@@ -1,0 +1,681 @@
+// cmflb_kernels.hip -- gfx950 kernels of libcmflb: the fused pull-stream +
+// central-moment collision step (D2Q9, D3Q27), its statistics finalize, and
+// the state conversion / diagnostic kernels.
+//
+// Method: De Rosis & Zhou, "A fluctuating lattice Boltzmann formulation based
+// on orthogonal central moments" (arXiv 2602.16486), Sec. 2.2 (D2Q9) and
+// Sec. 2.3 (D3Q27).  The per-site work follows the paper's "Algorithm of
+// computation": macroscopic moments (eq. macro), normals, pre-collision
+// central moments, collision (eq. cm_collision with phi of eq. phi_general),
+// back transformation f* = T(u)^-1 k*, streaming (eq. streaming).
+//
+// Memory layout: populations are structure-of-arrays, one plane of
+// `pstride` elements per population, site s = x + nx (y + ny z) inside a
+// plane, stored as deviations d_i = f_i - w_i rho0.  The buffer of step t
+// holds post-collision values of step t - 1 at their source site; step t
+// pulls d_i(x - c_i), collides, and writes d*_i(x) to the other buffer
+// (two-buffer pull scheme).  Every value is read once and written once per
+// step, so the step is HBM-bound at 2 Q sizeof(storage) bytes per site.
+//
+// Work decomposition: a tile is BX consecutive sites of one x-row
+// (BX = blockDim.x, a multiple of 64); a block walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... and keeps its statistics in
+// registers until the end, so the partial-sum traffic is one row per block.
+#include "cmflb_device.h"
+#include "cmflb_internal.h"
+
+namespace cmf {
+
+// ---------------------------------------------------------------------------
+// per-site collision
+// ---------------------------------------------------------------------------
+
+struct Acc {
+  double v[kNAcc];  // drho, j(3), u(3), u2(3), nonfinite
+};
+
+template <typename R>
+__device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
+  return __builtin_isfinite(a) && __builtin_isfinite(b) &&
+         __builtin_isfinite(c) && __builtin_isfinite(d);
+}
+
+// d: the Q pulled deviations (population order) in, the post-collision
+// deviations out.  GENERAL selects the full forward transform for arbitrary
+// Lambda; otherwise the rates follow the paper's pattern (Lambda = 1 except
+// the modes relaxed at omega: D2Q9 v = 4, 5; D3Q27 v = 7, 8, 9) and only
+// those pre-collision central moments are formed, as the paper does.
+template <class L, typename R, bool GENERAL>
+__device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
+                                             uint32_t site, uint32_t step,
+                                             Acc &acc) {
+  constexpr int Q = L::Q;
+  // step 1: rho = rho0 + sum d, rho u = sum c d (eq. macro)
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += d[i];
+    if (L::cx[i] > 0) jx += d[i];
+    if (L::cx[i] < 0) jx -= d[i];
+    if (L::cy[i] > 0) jy += d[i];
+    if (L::cy[i] < 0) jy -= d[i];
+    if (L::cz[i] > 0) jz += d[i];
+    if (L::cz[i] < 0) jz -= d[i];
+  }
+  const R rho = p.rho0 + drho;
+  const R irho = R(1) / rho;
+  const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
+
+  acc.v[0] += (double)drho;
+  acc.v[1] += (double)jx;
+  acc.v[2] += (double)jy;
+  acc.v[3] += (double)jz;
+  acc.v[4] += (double)ux;
+  acc.v[5] += (double)uy;
+  acc.v[6] += (double)uz;
+  acc.v[7] += (double)(ux * ux);
+  acc.v[8] += (double)(uy * uy);
+  acc.v[9] += (double)(uz * uz);
+  acc.v[10] += finite4(rho, ux, uy, uz) ? 0.0 : 1.0;
+
+  // step 2: normals of the noisy modes
+  R eta[L::NNOISE];
+  if (p.noise) {
+    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, eta);
+  } else {
+#pragma unroll
+    for (int n = 0; n < L::NNOISE; ++n) eta[n] = R(0);
+  }
+  const R sq = sqrt(rho);  // phi_v = sqrt(rho) amp_v (local rho)
+
+  R t[L::NT];
+  if constexpr (!GENERAL) {
+    // steps 3-4 with the paper's rates: only the modes relaxed at omega
+    // need their pre-collision value; every other noisy mode is pure noise
+    // around k_eq = 0.
+    if constexpr (Q == 27) {
+      R sxy = R(0), sxz = R(0), syz = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int pxy = L::cx[i] * L::cy[i], pxz = L::cx[i] * L::cz[i],
+                  pyz = L::cy[i] * L::cz[i];
+        if (pxy > 0) sxy += d[i];
+        if (pxy < 0) sxy -= d[i];
+        if (pxz > 0) sxz += d[i];
+        if (pxz < 0) sxz -= d[i];
+        if (pyz > 0) syz += d[i];
+        if (pyz < 0) syz -= d[i];
+      }
+      // k_7, k_8, k_9 (Sec. 2.3): sum f c_a c_b - rho u_a u_b; the rest
+      // weights do not contribute to the off-diagonal sums.
+      const R k7 = sxy - jx * uy, k8 = sxz - jx * uz, k9 = syz - jy * uz;
+      t[0] = rho;
+      t[1] = R(0);
+      t[3] = R(0);
+      t[9] = R(0);
+#pragma unroll
+      for (int n = 0; n < L::NNOISE; ++n) {
+        const int v = L::FIRST_NOISY + n;
+        R val = p.amp[v] * sq * eta[n];
+        if (v == 7) val += p.oml[7] * k7;
+        if (v == 8) val += p.oml[8] * k8;
+        if (v == 9) val += p.oml[9] * k9;
+        t[L::mode_pos[v]] = val;
+      }
+    } else {
+      R sd = R(0), sxy = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int dd = L::cx[i] * L::cx[i] - L::cy[i] * L::cy[i];
+        const int pxy = L::cx[i] * L::cy[i];
+        if (dd > 0) sd += d[i];
+        if (dd < 0) sd -= d[i];
+        if (pxy > 0) sxy += d[i];
+        if (pxy < 0) sxy -= d[i];
+      }
+      // k_4 = r_4 - rho (u_x^2 - u_y^2), k_5 = r_5 - rho u_x u_y (Sec. 2.2)
+      const R k4 = sd - (jx * ux - jy * uy);
+      const R k5 = sxy - jx * uy;
+      const R k3s = p.amp[3] * sq * eta[0];
+      const R k4s = p.oml[4] * k4 + p.amp[4] * sq * eta[1];
+      const R k5s = p.oml[5] * k5 + p.amp[5] * sq * eta[2];
+      t[0] = rho;
+      t[1] = R(0);
+      t[3] = R(0);
+      t[2] = R(0.5) * (k3s + k4s);  // P2(x) P0(y)
+      t[6] = R(0.5) * (k3s - k4s);  // P0(x) P2(y)
+      t[4] = k5s;
+      t[5] = p.amp[6] * sq * eta[3];
+      t[7] = p.amp[7] * sq * eta[4];
+      t[8] = p.amp[8] * sq * eta[5];
+    }
+  } else {
+    // steps 3-4 for arbitrary rates: k = T(u) f = T(u) d + rho0 G(u), then
+    // k*_v = (1 - Lambda_v) k_v + Lambda_v k_eq_v + I~_v phi_v eta_v with
+    // k_eq = (rho, 0, ..., 0).
+    const Axis<R> ax(ux), ay(uy), az(uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) t[pop_pos<L>(i)] = d[i];
+    tensor_fwd<L::D, R>(t, ax, ay, az);
+    add_rest_moments<L::D, R>(t, p.rho0, ux, uy, uz);
+    if constexpr (Q == 27) {
+      R k[27];
+#pragma unroll
+      for (int v = 0; v < 27; ++v) k[v] = t[L::mode_pos[v]];
+#pragma unroll
+      for (int v = 0; v < 27; ++v) {
+        R val = p.oml[v] * k[v];
+        if (v == 0) val += p.lam[0] * rho;
+        if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+        t[L::mode_pos[v]] = val;
+      }
+    } else {
+      R k[9];
+      k[0] = t[0];
+      k[1] = t[1];
+      k[2] = t[3];
+      k[3] = t[2] + t[6];
+      k[4] = t[2] - t[6];
+      k[5] = t[4];
+      k[6] = t[5];
+      k[7] = t[7];
+      k[8] = t[8];
+      R ks[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        R val = p.oml[v] * k[v];
+        if (v == 0) val += p.lam[0] * rho;
+        if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+        ks[v] = val;
+      }
+      t[0] = ks[0];
+      t[1] = ks[1];
+      t[3] = ks[2];
+      t[2] = R(0.5) * (ks[3] + ks[4]);
+      t[6] = R(0.5) * (ks[3] - ks[4]);
+      t[4] = ks[5];
+      t[5] = ks[6];
+      t[7] = ks[7];
+      t[8] = ks[8];
+    }
+  }
+  // steps 5-6: d* = T(u)^-1 (k* - rho0 G(u))
+  add_rest_moments<L::D, R>(t, -p.rho0, ux, uy, uz);
+  {
+    const Axis<R> ax(ux), ay(uy), az(uz);
+    tensor_inv<L::D, R>(t, ax, ay, az);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = t[pop_pos<L>(i)];
+}
+
+// ---------------------------------------------------------------------------
+// block reduction of the statistics accumulators (fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_store_acc(Acc &acc, double *out) {
+  __shared__ double sh[kMaxBlock / 64][kNAcc];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) {
+    double v = acc.v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wave][k] = v;
+  }
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  if (threadIdx.x < kNAcc) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_sub(int a, int c, int n) {
+  // (a - c) mod n for c in {-1, 0, 1}
+  int r = a - c;
+  r = r < 0 ? r + n : r;
+  r = r >= n ? r - n : r;
+  return r;
+}
+
+template <class L, typename S, typename R, bool GENERAL>
+__global__ __launch_bounds__(kMaxBlock) void k_step(
+    const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
+    const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
+  constexpr int Q = L::Q;
+  using ST = Store<S, R>;
+  const uint32_t step = (uint32_t)*step_ptr;
+  const int BX = blockDim.x;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  Acc acc;
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
+
+  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+    const int xb = tile % p.nxb;
+    const int row = tile / p.nxb;
+    const int y = row % ny;
+    const int z = row / ny;
+    const int x = xb * BX + (int)threadIdx.x;
+    if (x < nx) {
+      // source offsets of the pull f_i(x) <- f*_i(x - c_i)
+      const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+      int rowoff[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const int ys = wrap_sub(y, a - 1, ny);
+          const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+          rowoff[a][b] = (ys + ny * zs) * nx;
+        }
+      R d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int off = rowoff[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1];
+        d[i] = ST::load(src + (int64_t)i * p.pstride + off, p.scale[i]);
+      }
+      const int site = x + nx * (y + ny * z);
+      collide_site<L, R, GENERAL>(d, p, (uint32_t)site, step, acc);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        ST::store(dst + (int64_t)i * p.pstride + site, d[i], p.iscale[i]);
+    }
+  }
+  block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride);
+}
+
+// ---------------------------------------------------------------------------
+// statistics finalize: fixed-order FP64 sum of the block partials into the
+// series row of the current step, then advance the step counter
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(
+    const double *__restrict__ partials, int nparts, double *__restrict__ series,
+    int cap, int64_t *__restrict__ step_ptr, double mass0, int stats) {
+  __shared__ double sh[256][kNAcc];
+  const int tid = threadIdx.x;
+  const int64_t step = *step_ptr;
+  if (stats) {
+    double s[kNAcc];
+#pragma unroll
+    for (int k = 0; k < kNAcc; ++k) s[k] = 0.0;
+    for (int b = tid; b < nparts; b += 256)
+#pragma unroll
+      for (int k = 0; k < kNAcc; ++k) s[k] += partials[(int64_t)b * kPartStride + k];
+#pragma unroll
+    for (int k = 0; k < kNAcc; ++k) sh[tid][k] = s[k];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+      if (tid < h)
+#pragma unroll
+        for (int k = 0; k < kNAcc; ++k) sh[tid][k] += sh[tid + h][k];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double *row = series + (step % cap) * kSeriesStride;
+      row[0] = (double)step;
+      row[1] = mass0 + sh[0][0];
+#pragma unroll
+      for (int k = 1; k < kNAcc; ++k) row[1 + k] = sh[0][k];
+    }
+  }
+  if (tid == 0) *step_ptr = step + 1;
+}
+
+// ---------------------------------------------------------------------------
+// state conversion kernels (FP64 arithmetic)
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ int64_t shifted_site(const ConvParams &cp, int64_t s,
+                                                int i, int sign) {
+  // site s + sign * c_i, periodic
+  const int x = (int)(s % cp.nx);
+  const int64_t r = s / cp.nx;
+  const int y = (int)(r % cp.ny);
+  const int z = (int)(r / cp.ny);
+  const int xs = wrap_sub(x, -sign * L::cx[i], cp.nx);
+  const int ys = wrap_sub(y, -sign * L::cy[i], cp.ny);
+  const int zs = wrap_sub(z, -sign * L::cz[i], cp.nz);
+  return xs + (int64_t)cp.nx * (ys + (int64_t)cp.ny * zs);
+}
+
+// d_eq = f_eq(rho, u) - w rho0 = T(u)^-1 (rho e_0 - rho0 G(u)), evaluated at
+// site s and written to the buffer slot that the next pull reads from.
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_init_eq(const ConvParams cp,
+                                                 const double *__restrict__ rho,
+                                                 const double *__restrict__ u,
+                                                 S *__restrict__ buf) {
+  using ST = Store<S, double>;
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const double r = rho ? rho[s] : cp.rho0;
+  const double ux = u ? u[s] : 0.0, uy = u ? u[N + s] : 0.0,
+               uz = u ? u[2 * N + s] : 0.0;
+  double t[L::NT];
+#pragma unroll
+  for (int k = 0; k < L::NT; ++k) t[k] = 0.0;
+  t[0] = r;
+  add_rest_moments<L::D, double>(t, -cp.rho0, ux, uy, uz);
+  const Axis<double> ax(ux), ay(uy), az(uz);
+  tensor_inv<L::D, double>(t, ax, ay, az);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    ST::store(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+              t[pop_pos<L>(i)], cp.iscale[i]);
+}
+
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_set_state(const ConvParams cp,
+                                                   const double *__restrict__ f,
+                                                   S *__restrict__ buf) {
+  using ST = Store<S, double>;
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    ST::store(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+              f[(int64_t)i * N + s] - cp.w[i] * cp.rho0, cp.iscale[i]);
+}
+
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_get_state(const ConvParams cp,
+                                                   const S *__restrict__ buf,
+                                                   double *__restrict__ f) {
+  using ST = Store<S, double>;
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    f[(int64_t)i * N + s] =
+        cp.w[i] * cp.rho0 +
+        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+                 cp.scale[i]);
+}
+
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_gather(const ConvParams cp,
+                                                const S *__restrict__ buf,
+                                                const int64_t *__restrict__ sites,
+                                                int64_t n,
+                                                double *__restrict__ out) {
+  using ST = Store<S, double>;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t s = sites[k];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    out[k * L::Q + i] =
+        cp.w[i] * cp.rho0 +
+        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+                 cp.scale[i]);
+}
+
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
+                                               const S *__restrict__ buf,
+                                               float *__restrict__ rho_out,
+                                               float *__restrict__ u_out) {
+  using ST = Store<S, double>;
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const double d =
+        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+                 cp.scale[i]);
+    drho += d;
+    j[0] += L::cx[i] * d;
+    j[1] += L::cy[i] * d;
+    j[2] += L::cz[i] * d;
+  }
+  const double rho = cp.rho0 + drho;
+  if (rho_out) rho_out[s] = (float)rho;
+  if (u_out) {
+    u_out[s] = (float)(j[0] / rho);
+    u_out[N + s] = (float)(j[1] / rho);
+    u_out[2 * N + s] = (float)(j[2] / rho);
+  }
+}
+
+template <class L, typename R>
+__global__ __launch_bounds__(256) void k_noise(uint32_t key0, uint32_t key1,
+                                               uint32_t replica, uint32_t step,
+                                               int64_t site0, int64_t n,
+                                               double *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  R eta[L::NNOISE];
+  site_normals<L, R>((uint32_t)(site0 + k), step, replica, key0, key1, eta);
+  for (int v = 0; v < L::Q; ++v)
+    out[k * L::Q + v] =
+        v < L::FIRST_NOISY ? 0.0 : (double)eta[v - L::FIRST_NOISY];
+}
+
+__global__ __launch_bounds__(256) void k_philox(const uint32_t *__restrict__ ctr,
+                                                int64_t n, uint32_t key0,
+                                                uint32_t key1,
+                                                uint32_t *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const U4 w = philox4x32_10(ctr[4 * k], ctr[4 * k + 1], ctr[4 * k + 2],
+                             ctr[4 * k + 3], key0, key1);
+  out[4 * k] = w.x;
+  out[4 * k + 1] = w.y;
+  out[4 * k + 2] = w.z;
+  out[4 * k + 3] = w.w;
+}
+
+__global__ void k_zero_i64(int64_t *p, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class L, typename S, typename R, bool G>
+hipError_t step_one(const void *params, const void *src, void *dst,
+                    const int64_t *step_ptr, double *partials, int grid,
+                    int block, hipStream_t stream) {
+  const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
+  hipLaunchKernelGGL((k_step<L, S, R, G>), dim3(grid), dim3(block), 0, stream,
+                     static_cast<const S *>(src), static_cast<S *>(dst), p,
+                     step_ptr, partials);
+  return hipGetLastError();
+}
+
+template <class L, typename S, typename R>
+hipError_t step_lg(bool general, const void *params, const void *src, void *dst,
+                   const int64_t *step_ptr, double *partials, int grid,
+                   int block, hipStream_t stream) {
+  return general ? step_one<L, S, R, true>(params, src, dst, step_ptr, partials,
+                                           grid, block, stream)
+                 : step_one<L, S, R, false>(params, src, dst, step_ptr,
+                                            partials, grid, block, stream);
+}
+
+template <class L>
+hipError_t step_l(int storage, bool general, const void *params,
+                  const void *src, void *dst, const int64_t *step_ptr,
+                  double *partials, int grid, int block, hipStream_t stream) {
+  switch (storage) {
+    case kF64:
+      return step_lg<L, double, double>(general, params, src, dst, step_ptr,
+                                        partials, grid, block, stream);
+    case kF32:
+      return step_lg<L, float, float>(general, params, src, dst, step_ptr,
+                                      partials, grid, block, stream);
+    case kF16:
+      return step_lg<L, __half, float>(general, params, src, dst, step_ptr,
+                                       partials, grid, block, stream);
+    case kBF16:
+      return step_lg<L, __hip_bfloat16, float>(general, params, src, dst,
+                                               step_ptr, partials, grid, block,
+                                               stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_step(int q, int storage, bool general, const void *params,
+                       const void *src, void *dst, const int64_t *step_ptr,
+                       double *partials, int grid, int block,
+                       hipStream_t stream) {
+  if (q == 9)
+    return step_l<D2Q9>(storage, general, params, src, dst, step_ptr, partials,
+                        grid, block, stream);
+  if (q == 27)
+    return step_l<D3Q27>(storage, general, params, src, dst, step_ptr,
+                         partials, grid, block, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const double *partials, int nparts, double *series,
+                           int cap, int64_t *step_ptr, double mass0, bool stats,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, partials, nparts,
+                     series, cap, step_ptr, mass0, stats ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <class T>
+struct Tag {
+  using type = T;
+};
+
+// call f(Tag<Lattice>, Tag<StorageType>) for a runtime (q, storage)
+template <class F>
+hipError_t with_lattice_storage(int q, int storage, F &&f) {
+  auto by_storage = [&](auto lt) -> hipError_t {
+    switch (storage) {
+      case kF64: return f(lt, Tag<double>{});
+      case kF32: return f(lt, Tag<float>{});
+      case kF16: return f(lt, Tag<__half>{});
+      case kBF16: return f(lt, Tag<__hip_bfloat16>{});
+    }
+    return hipErrorInvalidValue;
+  };
+  if (q == 9) return by_storage(Tag<D2Q9>{});
+  if (q == 27) return by_storage(Tag<D3Q27>{});
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_init_eq(int q, int storage, const ConvParams &cp,
+                          const double *rho, const double *u, void *buf,
+                          hipStream_t stream) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_init_eq<L, S>), dim3(blocks_for(N, 256)), dim3(256),
+                       0, stream, cp, rho, u, static_cast<S *>(buf));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_set_state(int q, int storage, const ConvParams &cp,
+                            const double *f, void *buf, hipStream_t stream) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_set_state<L, S>), dim3(blocks_for(N, 256)),
+                       dim3(256), 0, stream, cp, f, static_cast<S *>(buf));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_get_state(int q, int storage, const ConvParams &cp,
+                            const void *buf, double *f, hipStream_t stream) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_get_state<L, S>), dim3(blocks_for(N, 256)),
+                       dim3(256), 0, stream, cp, static_cast<const S *>(buf), f);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_gather(int q, int storage, const ConvParams &cp,
+                         const void *buf, const int64_t *sites, int64_t n,
+                         double *out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_gather<L, S>), dim3(blocks_for(n, 256)), dim3(256), 0,
+                       stream, cp, static_cast<const S *>(buf), sites, n, out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_macro(int q, int storage, const ConvParams &cp,
+                        const void *buf, float *rho, float *u,
+                        hipStream_t stream) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_macro<L, S>), dim3(blocks_for(N, 256)), dim3(256), 0,
+                       stream, cp, static_cast<const S *>(buf), rho, u);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
+                        uint32_t replica, uint32_t step, int64_t site0,
+                        int64_t n, double *out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = blocks_for(n, 256);
+  if (q == 9) {
+    if (fp64)
+      hipLaunchKernelGGL((k_noise<D2Q9, double>), dim3(g), dim3(256), 0, stream,
+                         key0, key1, replica, step, site0, n, out);
+    else
+      hipLaunchKernelGGL((k_noise<D2Q9, float>), dim3(g), dim3(256), 0, stream,
+                         key0, key1, replica, step, site0, n, out);
+  } else if (q == 27) {
+    if (fp64)
+      hipLaunchKernelGGL((k_noise<D3Q27, double>), dim3(g), dim3(256), 0,
+                         stream, key0, key1, replica, step, site0, n, out);
+    else
+      hipLaunchKernelGGL((k_noise<D3Q27, float>), dim3(g), dim3(256), 0, stream,
+                         key0, key1, replica, step, site0, n, out);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
+                         uint32_t key1, uint32_t *out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, stream,
+                     ctr, n, key0, key1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i64, dim3(blocks_for(n, 256)), dim3(256), 0, stream,
+                     p, n);
+  return hipGetLastError();
+}
+
+}  // namespace cmf

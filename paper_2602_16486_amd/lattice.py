@@ -1,0 +1,128 @@
+"""Python-side handle of one lattice of libcmflb (a thin wrapper of the C ABI;
+every computation runs in the HIP kernels)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+
+class Lattice:
+    """A periodic D2Q9 or D3Q27 box stepped by the fused CM-FLBM kernel.
+
+    ``shape`` is (nx, ny) or (nx, ny, nz); ``storage`` one of f64, f32, f16,
+    bf16; ``lam`` optional per-mode relaxation rates (default: the paper's);
+    ``stream`` an optional hipStream_t handle (int), e.g.
+    ``torch.cuda.current_stream().cuda_stream``.
+    """
+
+    def __init__(self, q, shape, storage="f32", rho0=1.0, tau=0.8, kT=0.0, lam=None, seed=1,
+                 replica=0, flags=0, stream=None, series_capacity=0):
+        self._lib = _lib.load()
+        nx, ny, nz = (tuple(int(s) for s in shape) + (1, 1))[:3]
+        self.q = int(q)
+        self.shape = (nx, ny, nz)
+        self.n = nx * ny * nz
+        self.storage = storage
+        d = _lib.Desc()
+        d.q, d.nx, d.ny, d.nz = self.q, nx, ny, nz
+        d.storage = _lib.STORAGE[storage]
+        d.flags = flags
+        d.rho0, d.tau, d.kT = float(rho0), float(tau), float(kT)
+        self._lam = None
+        if lam is not None:
+            self._lam = np.ascontiguousarray(lam, dtype=np.float64)
+            if self._lam.shape != (self.q,):
+                raise ValueError(f"lam must have {self.q} entries")
+            d.lam = self._lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.seed = int(seed)
+        d.replica = int(replica)
+        d.series_capacity = int(series_capacity)
+        self.rho0, self.tau, self.kT = float(rho0), float(tau), float(kT)
+        handle = ctypes.c_void_p()
+        _lib.check(self._lib.cmf_create(ctypes.byref(d), ctypes.c_void_p(stream or 0),
+                                        ctypes.byref(handle)))
+        self._h = handle
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state --------------------------------------------------------------
+    def init_equilibrium(self, rho=None, u=None):
+        r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(self.n)
+        uu = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3, self.n)
+        _lib.check(self._lib.cmf_init_equilibrium(
+            self._h, None if r is None else _lib._d(r), None if uu is None else _lib._d(uu)))
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (self.q, self.n):
+            raise ValueError(f"populations must have shape {(self.q, self.n)}")
+        _lib.check(self._lib.cmf_set_populations(self._h, _lib._d(f)))
+
+    def get_populations(self):
+        f = np.zeros((self.q, self.n))
+        _lib.check(self._lib.cmf_get_populations(self._h, _lib._d(f)))
+        return f
+
+    def gather_sites(self, sites):
+        s = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.zeros((s.size, self.q))
+        _lib.check(self._lib.cmf_gather_sites(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              s.size, _lib._d(out)))
+        return out
+
+    # -- stepping -----------------------------------------------------------
+    def step(self, n=1):
+        _lib.check(self._lib.cmf_step(self._h, int(n)))
+
+    def profile_steps(self, n):
+        """Run n direct-launch steps with HIP events around each fused-step
+        kernel; returns the summed kernel time in milliseconds."""
+        ms = ctypes.c_double()
+        _lib.check(self._lib.cmf_profile_steps(self._h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def synchronize(self):
+        _lib.check(self._lib.cmf_synchronize(self._h))
+
+    @property
+    def step_index(self):
+        v = ctypes.c_int64()
+        _lib.check(self._lib.cmf_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    def stats(self, cap=1 << 20, raise_nonfinite=True):
+        """(n, 12) array of the per-step statistics rows recorded since the
+        previous call (columns ``_lib.STAT_COLUMNS``)."""
+        buf = (_lib.Moments * cap)()
+        n = ctypes.c_int64()
+        rc = self._lib.cmf_stats(self._h, buf, cap, ctypes.byref(n))
+        out = np.frombuffer(buf, dtype=np.float64, count=12 * n.value).reshape(n.value, 12).copy()
+        if rc == _lib.CMF_ENONFINITE and not raise_nonfinite:
+            return out
+        _lib.check(rc)
+        return out
+
+    def sample_macro(self, rho_ptr, u_ptr):
+        """Write rho (N floats) and u (3N floats) into device buffers given as
+        raw device pointers (ints), e.g. ``tensor.data_ptr()``."""
+        _lib.check(self._lib.cmf_sample_macro(self._h, ctypes.c_void_p(rho_ptr or 0),
+                                              ctypes.c_void_p(u_ptr or 0)))

@@ -1,0 +1,87 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+declared in include/cmflb.h, and rejects invalid descriptors before touching
+a device.  CPU only (no compute calls)."""
+import ctypes
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2602_16486_amd import _lib
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    names = _lib.declared_functions()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_version_and_error_string():
+    assert _lib.version().startswith("cmflb")
+    lib = _lib.load()
+    assert isinstance(lib.cmf_last_error(), bytes)
+
+
+def _create(**kw):
+    d = _lib.Desc()
+    d.q, d.nx, d.ny, d.nz = kw.get("q", 9), kw.get("nx", 8), kw.get("ny", 8), kw.get("nz", 1)
+    d.storage = kw.get("storage", 1)
+    d.rho0, d.tau, d.kT = kw.get("rho0", 1.0), kw.get("tau", 0.8), kw.get("kT", 1e-4)
+    lam = kw.get("lam")
+    if lam is not None:
+        arr = (ctypes.c_double * len(lam))(*lam)
+        d.lam = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    d.series_capacity = kw.get("series_capacity", 0)
+    h = ctypes.c_void_p()
+    rc = _lib.load().cmf_create(ctypes.byref(d), None, ctypes.byref(h))
+    return rc, _lib.load().cmf_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"q": 10}, "q must be 9 or 27"),
+    ({"q": 9, "nz": 2}, "D2Q9 needs nz = 1"),
+    ({"nx": 0}, "box edges"),
+    ({"q": 27, "nx": 2048, "ny": 1024, "nz": 1024}, "exceeds 2^31"),
+    ({"storage": 7}, "unknown storage"),
+    ({"rho0": 0.0}, "rho0"),
+    ({"tau": 0.49}, "tau"),
+    ({"kT": -1e-4}, "kT"),
+    ({"lam": [1.0] * 8 + [2.5]}, "outside [0, 2]"),
+    ({"series_capacity": -1}, "series_capacity"),
+])
+def test_create_rejects_invalid_descriptors(kw, msg):
+    rc, err = _create(**kw)
+    assert rc == _lib.CMF_EINVAL
+    assert msg in err
+
+
+def test_null_arguments_are_rejected():
+    lib = _lib.load()
+    assert lib.cmf_create(None, None, None) == _lib.CMF_EINVAL
+    assert lib.cmf_step(None, 1) == _lib.CMF_EINVAL
+    assert lib.cmf_destroy(None) == _lib.CMF_EINVAL
+    assert lib.cmf_noise_sample(10, 1, 0, 0, 0, 4, 0, None) == _lib.CMF_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The binding never falls back to a CPU path: without the built library,
+    creating a lattice raises."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2602_16486_amd._lib as L\n"
+        "L.library_path = lambda: %r\n"
+        "import paper_2602_16486_amd as P\n"
+        "try:\n"
+        "    P.Lattice(9, (8, 8))\n"
+        "except ImportError as e:\n"
+        "    print('raised', e)\n" % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                      str(tmp_path / "absent.so")))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert "raised" in out.stdout and "no CPU fallback" in out.stdout

@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on
+identical seeded inputs.  Needs an MI355X.
+
+Tolerances (derivation in the design notes):
+  * Philox words: bit-exact.
+  * FP64 path (F64 storage): populations within 1e-12 of the oracle, relative
+    to the largest deviation |f - w rho0| -- both sides are FP64 and differ
+    only in rounding order and libm ulps.
+  * FP32 path: normals within 4e-6 absolute; populations within
+    F32_TOL(steps) = 3e-6 * (1 + sqrt(steps)) relative to the largest
+    deviation: FP32 rounds each deviation to ~6e-8 of itself per operation
+    and the conserved modes keep (do not damp) what rounding adds, so the
+    error grows like a random walk in the number of steps.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_16486_amd import Lattice, _lib
+from paper_2602_16486_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+
+
+def F32_TOL(steps):
+    return 3e-6 * (1.0 + math.sqrt(steps))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu_present():
+    assert _lib.device_count() > 0, "no HIP device visible: the gpu tests need an MI355X"
+
+
+def _rel_err(f_gpu, f_ref, q):
+    _, w = O.lattice(q)
+    scale = np.abs(f_ref - w[:, None] * 1.0).max()
+    return np.abs(f_gpu - f_ref).max() / max(scale, 1e-300)
+
+
+def _random_state(q, shape, seed, rho0=1.0, umax=0.05, amp=1e-3):
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, seed, rho0=rho0, umax=umax, dims=2 if q == 9 else 3)
+    return O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, seed + 1, amp)
+
+
+# ---- noise ----------------------------------------------------------------
+
+def test_philox_words_bit_exact():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 1 << 32, (4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [1, 2, 3, 4], [7, 0, 0, 5]]
+    for key in [(0, 0), (0xFFFFFFFF, 0xFFFFFFFF), (12345, 678)]:
+        got = _lib.philox_words(ctr, *key)
+        ref = np.array([O.philox4x32_10(c, key) for c in ctr])
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("q", [9, 27])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_normals_match_oracle(q, fp64):
+    n, site0, step, seed, replica = 3000, 123456, 77, (1 << 40) + 5, 3
+    got = _lib.noise_sample(q, seed, replica, step, site0, n, fp64=fp64)
+    ref = np.array([O.normals(q, seed, replica, step, site0 + k) for k in range(n)])
+    tol = 1e-13 if fp64 else 4e-6
+    assert np.abs(got - ref).max() < tol
+
+
+# ---- state conversion -----------------------------------------------------
+
+@pytest.mark.parametrize("q,shape", [(9, (37, 23)), (27, (13, 9, 7))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_init_equilibrium_matches_oracle(q, shape, storage):
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, 5, rho0=1.1, umax=0.1, dims=2 if q == 9 else 3)
+    with Lattice(q, shape, storage=storage, rho0=1.1, kT=1e-4) as lat:
+        lat.init_equilibrium(rho, u)
+        got = lat.get_populations()
+        assert lat.step_index == 0
+    ref = O.init_equilibrium(q, n, rho=rho, u=u)
+    tol = 1e-15 if storage == "f64" else 1e-7
+    assert _rel_err(got, ref, q) < tol
+
+
+@pytest.mark.parametrize("q,shape", [(9, (300, 5)), (27, (70, 6, 5))])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_set_get_roundtrip(q, shape, storage):
+    f = _random_state(q, shape, 9)
+    with Lattice(q, shape, storage=storage, kT=1e-4) as lat:
+        lat.set_populations(f)
+        got = lat.get_populations()
+        sites = W.sample_sites(shape, 50, 3)
+        g = lat.gather_sites(sites)
+    _, w = O.lattice(q)
+    dev = f - w[:, None]
+    if storage == "f64":
+        assert np.array_equal(got, f)
+    else:
+        rel = {"f32": 2 ** -24, "f16": 2 ** -11, "bf16": 2 ** -8}[storage]
+        # rounding is relative to the deviation, not to f (plus the FP16
+        # subnormal spacing 2^-24 s_i, below 1e-10 for these scales)
+        assert np.all(np.abs(got - f) <= rel * np.abs(dev) * 1.0001 + 1e-10)
+    assert np.array_equal(g, got[:, sites].T)
+
+
+# ---- one step and many steps ---------------------------------------------
+
+@pytest.mark.parametrize("q,shape", [(9, (300, 7)), (27, (300, 4, 3)), (27, (37, 5, 6))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("general", [False, True])
+def test_one_step_matches_oracle(q, shape, storage, general):
+    f = _random_state(q, shape, 21)
+    kT, tau, seed, replica = 2e-4, 0.7, 99, 4
+    lam = None
+    if general:
+        lam = np.linspace(0.4, 1.9, q)
+        lam_o = lam
+    else:
+        lam_o = O.paper_lambda(q, 1 / tau)
+    with Lattice(q, shape, storage=storage, tau=tau, kT=kT, lam=lam, seed=seed,
+                 replica=replica) as lat:
+        lat.set_populations(f)
+        lat.step(1)
+        got = lat.get_populations()
+        st = lat.stats()
+    g = f.copy()
+    ref_st = O.run(q, shape, g, kT, lam_o, seed, replica, step0=0, nsteps=1)
+    tol = F64_TOL if storage == "f64" else F32_TOL(1)
+    assert _rel_err(got, g, q) < tol
+    assert st.shape == (1, 12)
+    assert st[0, 0] == 0
+    n = W.n_sites(shape)
+    # statistics of the pre-collision state: exact up to summation order
+    assert st[0, 1] == pytest.approx(ref_st[0, 1], rel=1e-13 if storage == "f64" else 1e-9)
+    assert np.allclose(st[0, 2:11], ref_st[0, 2:11], rtol=1e-5 if storage == "f32" else 1e-10,
+                       atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_config1_prefix_matches_oracle(storage):
+    """D2Q9 64x64, rho0 = 1, tau = 0.8, kT = 1e-4, Philox seed 1, from rest:
+    the first 200 steps against the oracle, fields and statistics."""
+    q, shape, kT, steps = 9, (64, 64), 1e-4, 200
+    with Lattice(q, shape, storage=storage, tau=0.8, kT=kT, seed=1) as lat:
+        lat.step(steps)
+        got = lat.get_populations()
+        st = lat.stats()
+    f = O.init_equilibrium(q, 4096, rho0=1.0)
+    ref = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), 1, 0, 0, steps)
+    tol = F64_TOL if storage == "f64" else F32_TOL(steps)
+    err = _rel_err(got, f, q)
+    print(f"config1 prefix {storage}: rel err {err:.3e} (tol {tol:.1e})")
+    assert err < tol
+    assert np.array_equal(st[:, 0], np.arange(steps))
+    rtol = 1e-10 if storage == "f64" else 50 * F32_TOL(steps)
+    assert np.allclose(st[:, 8:10], ref[:, 8:10], rtol=rtol, atol=1e-14)
+    assert np.abs(st[:, 1] - ref[:, 1]).max() < 1e-9
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("general", [False, True])
+def test_d3q27_multistep_matches_oracle(storage, general):
+    q, shape, kT, steps = 27, (20, 18, 16), 1e-4, 12
+    f0 = _random_state(q, shape, 31, umax=0.04)
+    lam = np.full(q, 1 / 0.55) if general else None
+    lam_o = lam if general else O.paper_lambda(q, 1 / 0.55)
+    with Lattice(q, shape, storage=storage, tau=0.55, kT=kT, seed=7, lam=lam) as lat:
+        lat.set_populations(f0)
+        lat.step(steps)
+        got = lat.get_populations()
+    f = f0.copy()
+    O.run(q, shape, f, kT, lam_o, 7, 0, 0, steps)
+    tol = F64_TOL if storage == "f64" else F32_TOL(steps)
+    err = _rel_err(got, f, q)
+    print(f"d3q27 {storage} general={general}: rel err {err:.3e} (tol {tol:.1e})")
+    assert err < tol
+
+
+# ---- invariants of the implementation -------------------------------------
+
+@pytest.mark.parametrize("q,shape", [(9, (40, 30)), (27, (12, 10, 8))])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_zero_noise_rest_state_is_exact(q, shape, storage):
+    """Test 1: kT = 0 from rest stays exactly at rest (deviations stay 0)."""
+    _, w = O.lattice(q)
+    with Lattice(q, shape, storage=storage, kT=0.0) as lat:
+        lat.step(40)
+        got = lat.get_populations()
+        st = lat.stats()
+    assert np.array_equal(got, np.repeat(w[:, None], W.n_sites(shape), axis=1))
+    assert np.all(st[:, 5:] == 0.0)
+
+
+def test_graph_replay_equals_direct_launches():
+    q, shape = 27, (40, 12, 10)
+    f0 = _random_state(q, shape, 41)
+    res = []
+    for flags in (0, _lib.FLAG_NO_GRAPH):
+        with Lattice(q, shape, storage="f32", kT=1e-4, seed=3, flags=flags) as lat:
+            lat.set_populations(f0)
+            lat.step(70)  # two graph replays + 6 direct steps
+            res.append((lat.get_populations(), lat.stats()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("grid,block", [("1", "64"), ("7", "128"), ("100000", "256")])
+def test_results_do_not_depend_on_launch_shape(monkeypatch, grid, block):
+    q, shape = 27, (150, 7, 5)
+    f0 = _random_state(q, shape, 43)
+    with Lattice(q, shape, storage="f32", kT=1e-4, seed=3) as lat:
+        lat.set_populations(f0)
+        lat.step(5)
+        ref = lat.get_populations()
+    monkeypatch.setenv("CMF_GRID", grid)
+    monkeypatch.setenv("CMF_BLOCK", block)
+    with Lattice(q, shape, storage="f32", kT=1e-4, seed=3) as lat:
+        lat.set_populations(f0)
+        lat.step(5)
+        got = lat.get_populations()
+    assert np.array_equal(got, ref)
+
+
+def test_nonfinite_is_reported():
+    """A thermal energy far beyond the low-Mach regime drives rho negative;
+    the statistics report non-finite sites and cmf_stats returns
+    CMF_ENONFINITE."""
+    with Lattice(9, (16, 16), storage="f32", kT=50.0, seed=2) as lat:
+        lat.step(20)
+        with pytest.raises(_lib.CmfError) as exc:
+            lat.stats()
+        assert exc.value.code == _lib.CMF_ENONFINITE
+
+
+def test_mass_and_momentum_conserved_fp64():
+    q, shape = 27, (24, 20, 16)
+    f0 = _random_state(q, shape, 47)
+    with Lattice(q, shape, storage="f64", kT=1e-3, seed=5) as lat:
+        lat.set_populations(f0)
+        lat.step(100)
+        st = lat.stats()
+    assert np.ptp(st[:, 1]) / st[0, 1] < 1e-13
+    assert np.abs(st[:, 2:5] - st[0, 2:5]).max() / st[0, 1] < 1e-14
+
+
+# ---- full size: the bench workload, sampled --------------------------------
+
+def test_full_size_d3q27_256_sampled_one_step():
+    """D3Q27 256^3, FP32 storage, in the benchmark's launch configuration:
+    after 20 steps from rest, one more step is checked at sampled sites
+    (random plus every box corner/edge midpoint) against the oracle's
+    single-site collision of the gathered pre-collision populations."""
+    q, shape, kT, tau, seed = 27, (256, 256, 256), 1e-4, 0.8, 1
+    nx, ny, nz = shape
+    c, _ = O.lattice(q)
+    sites = W.sample_sites(shape, 1500, 11)
+    with Lattice(q, shape, storage="f32", tau=tau, kT=kT, seed=seed) as lat:
+        lat.step(20)
+        t = lat.step_index
+        pre = lat.gather_sites(sites)
+        lat.step(1)
+        x, y, z = sites % nx, (sites // nx) % ny, sites // (nx * ny)
+        dest = np.stack([((x + c[i, 0]) % nx) + nx * (((y + c[i, 1]) % ny) + ny * ((z + c[i, 2]) % nz))
+                         for i in range(q)], axis=1)
+        post = lat.gather_sites(dest.ravel()).reshape(len(sites), q, q)
+    lam = O.paper_lambda(q, 1 / tau)
+    _, w = O.lattice(q)
+    worst = 0.0
+    for k, s in enumerate(sites):
+        eta = O.normals(q, seed, 0, t, int(s))
+        fs = O.collide_site(q, pre[k], eta, kT, lam)["fstar"]
+        got = np.array([post[k, i, i] for i in range(q)])
+        worst = max(worst, np.abs(got - fs).max() / np.abs(fs - w).max())
+    print(f"256^3 sampled one-step rel err {worst:.3e}")
+    assert worst < F32_TOL(1)
