@@ -15,6 +15,7 @@ CPU oracle's throughput on a bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -39,11 +40,42 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_storage(storage, steps, warmup, stream, torch):
+KERNEL_SOURCES = ("paper_2602_16486_amd/csrc/cmflb_kernels.hip",
+                  "paper_2602_16486_amd/csrc/cmflb_device.h",
+                  "paper_2602_16486_amd/csrc/cmflb_internal.h")
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_d3q27_f32_256cube.counters.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the FP32 step kernel from the committed
+    rocprofv3 counter passes, if they were taken on these kernel sources and
+    this launch shape; otherwise None."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != kernel_source_hash() or list(c.get("launch", [])) != list(launch):
+        return None
+    return c["traffic_bytes_per_launch"]
+
+
+def time_storage(storage, steps, warmup, stream, torch, tune=True):
     from paper_2602_16486_amd import Lattice
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
     with Lattice(Q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
                  stream=stream.cuda_stream, series_capacity=8192) as lat:
+        if tune:
+            lat.autotune(steps_per_trial=10)  # untimed; state restored
+        launch = lat.launch
         lat.step(warmup)
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
@@ -63,6 +95,7 @@ def time_storage(storage, steps, warmup, stream, torch):
     # equipartition over the recorded steps after the first 30 (warm-up)
     u2 = st[30:, 8:11].sum(axis=1) / (3 * n)
     return {
+        "launch": launch,
         "ms_per_step": ms_step,
         "glups": glups,
         "kernel_ms": kernel_ms,
@@ -79,7 +112,7 @@ def cpu_baseline():
     import numpy as np  # noqa: F401
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    shape, steps = (64, 64, 64), 40
+    shape, steps = (64, 64, 64), 160
     n = shape[0] * shape[1] * shape[2]
     f = O.init_equilibrium(Q, n, rho0=RHO0)
     t0 = time.perf_counter()
@@ -97,6 +130,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--variants", default="f16,bf16")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,22 +150,27 @@ def main():
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
 
     log(f"timing f32: {args.warmup} warm-up + {args.steps} timed steps")
-    main_run = time_storage("f32", args.steps, args.warmup, stream, torch)
+    main_run = time_storage("f32", args.steps, args.warmup, stream, torch, tune=not args.no_tune)
     log(f"f32: {main_run['ms_per_step']:.4f} ms/step, {main_run['glups']:.2f} GLUPS")
     variants = {}
     for storage in [s for s in args.variants.split(",") if s]:
         log(f"timing {storage}")
-        r = time_storage(storage, args.steps, args.warmup, stream, torch)
+        r = time_storage(storage, args.steps, args.warmup, stream, torch, tune=not args.no_tune)
         m = min(len(r["u2_series"]), len(main_run["u2_series"]))
         du = float(np.abs(r["u2_series"][:m].mean() / main_run["u2_series"][:m].mean() - 1))
         variants[storage] = {
             "value": r["glups"], "ms_per_step": r["ms_per_step"],
             "kernel_gbs": r["kernel_gbs"], "frac_hbm": r["kernel_gbs"] / PEAK_HBM_GBS,
+            "launch": list(r["launch"]),
             "bytes_per_site": bytes_per_site(storage),
             "u2_over_kT": r["u2_over_kT"], "u2_rel_diff_vs_f32": du,
         }
         log(f"{storage}: {r['glups']:.2f} GLUPS, <u2> rel diff vs f32 {du:.2e}")
 
+    copy_bytes = Q * n * 4  # one FP32 population buffer: the step's footprint
+    copy_ms = _lib.stream_copy(copy_bytes, reps=5)
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    log(f"plain copy of {copy_bytes / 1e9:.2f} GB: {copy_gbs:.0f} GB/s")
     achieved = main_run["kernel_gbs"]
     result = {
         "metric": "D3Q27 256^3 GLUPS (fused fluctuating CM step)",
@@ -151,6 +190,7 @@ def main():
                         "FP32 deviation storage, FP32 collide, FP64 per-step statistics",
             "lattice": "D3Q27", "box": list(SHAPE), "storage": "f32",
             "bytes_per_site_step": bytes_per_site("f32"),
+            "launch": list(main_run["launch"]),
         },
         "roofline": {
             "bound": "hbm",
@@ -158,9 +198,11 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(main_run["launch"]),
             "kernel_ms": main_run["kernel_ms"],
             "bytes_per_launch": bytes_per_site("f32") * n,
+            "copy_ceiling_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "u2_over_kT": main_run["u2_over_kT"],
         "variants": variants,

@@ -156,6 +156,39 @@ int cmf_step(cmf_lattice *lat, int64_t nsteps);
  * steps are real steps: the state and the statistics advance. */
 int cmf_profile_steps(cmf_lattice *lat, int64_t nsteps, double *kernel_ms);
 
+/* One launch shape of the fused-step kernel: `block` threads per workgroup
+ * (a multiple of 64, at most 256; a workgroup covers `block` consecutive
+ * sites of an x-row per tile) and `grid` workgroups, each walking tiles
+ * blockIdx, blockIdx + grid, ... */
+typedef struct {
+  int32_t block;
+  int32_t grid;
+  double ms_per_step; /* measured by cmf_autotune; 0 otherwise */
+} cmf_launch;
+
+/* Current launch shape of the lattice's step kernel. */
+int cmf_get_launch(cmf_lattice *lat, cmf_launch *out);
+
+/* Set the launch shape: block in {64, 128, 192, 256}, grid >= 1 (capped at
+ * the number of tiles).  Results do not depend on it (the noise is keyed by
+ * the site), only the speed and the summation order of the statistics.
+ * Synchronises; drops captured graphs. */
+int cmf_set_launch(cmf_lattice *lat, int32_t block, int32_t grid);
+
+/* Autotuner: time every candidate launch shape (block 64..256 up to the
+ * row length; grid 1, 2, 4, 8, 16 and 32 x the compute-unit count, and one
+ * tile per workgroup) with `steps_per_trial` real steps each (after one
+ * untimed step; a step = fused kernel + statistics finalize), then restore the state, step counter and statistics ring
+ * exactly as they were and keep the fastest shape.  The best shape is
+ * remembered for the process under (device, q, storage, rates kind, box)
+ * and used by later cmf_create calls with the same key; when the environment
+ * variable CMFLB_TUNE_CACHE names a file, entries are also read from and
+ * appended to it.  Up to `cap` trials are written to `trials` (may be NULL);
+ * *n_out (may be NULL) receives the number of trials.  Needs one temporary
+ * buffer the size of the population state.  Synchronous. */
+int cmf_autotune(cmf_lattice *lat, int32_t steps_per_trial, cmf_launch *trials,
+                 int32_t cap, int32_t *n_out);
+
 /* Wait for all work enqueued on the lattice's stream. */
 int cmf_synchronize(cmf_lattice *lat);
 
@@ -188,6 +221,14 @@ int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step,
  * key, computed on the device; out receives 4n words.  Synchronous. */
 int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0,
                      uint32_t key1, uint32_t *out);
+
+/* Diagnostic: practical HBM ceiling.  Allocates two device buffers of
+ * `bytes` bytes (rounded up to 16), copies one into the other `reps` times
+ * with a plain streaming copy kernel (`cmf_stream_copy_kernel`, 16-byte
+ * vector loads and stores, each byte read once and written once), and
+ * returns the fastest copy in *best_ms.  Uses the null stream; synchronous;
+ * frees its buffers. */
+int cmf_stream_copy(size_t bytes, int32_t reps, double *best_ms);
 
 #ifdef __cplusplus
 }

@@ -56,6 +56,10 @@ class Desc(ctypes.Structure):
     ]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+
+
 class Moments(ctypes.Structure):
     _fields_ = [("v", ctypes.c_double * 12)]
 
@@ -65,7 +69,9 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def library_path():
-    return os.path.join(HERE, "libcmflb.so")
+    """The in-tree build, or the file named by CMFLB_LIBRARY (an alternative
+    build of the same sources, e.g. a tuning variant)."""
+    return os.environ.get("CMFLB_LIBRARY") or os.path.join(HERE, "libcmflb.so")
 
 
 def load():
@@ -100,7 +106,11 @@ def load():
     lib.cmf_noise_sample.argtypes = [i32, u64, u32, u32, i64, i64, i32, _dp]
     lib.cmf_philox_words.argtypes = [ctypes.POINTER(ctypes.c_uint32), i64, u32, u32,
                                      ctypes.POINTER(ctypes.c_uint32)]
-    for name in ("cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
+    lib.cmf_stream_copy.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.cmf_get_launch.argtypes = [vp, ctypes.POINTER(Launch)]
+    lib.cmf_set_launch.argtypes = [vp, i32, i32]
+    lib.cmf_autotune.argtypes = [vp, i32, ctypes.POINTER(Launch), i32, ctypes.POINTER(ctypes.c_int32)]
+    for name in ("cmf_get_launch", "cmf_set_launch", "cmf_autotune", "cmf_stream_copy", "cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
                  "cmf_get_populations", "cmf_gather_sites", "cmf_step", "cmf_synchronize",
                  "cmf_get_step", "cmf_stats", "cmf_sample_macro", "cmf_noise_sample",
                  "cmf_philox_words", "cmf_device_count", "cmf_profile_steps"):
@@ -149,3 +159,10 @@ def philox_words(ctr, key0, key1):
     up = ctypes.POINTER(ctypes.c_uint32)
     check(lib.cmf_philox_words(c.ctypes.data_as(up), c.shape[0], key0, key1, out.ctypes.data_as(up)))
     return out
+
+
+def stream_copy(nbytes, reps=5):
+    """Fastest plain device copy of nbytes (ms): read nbytes + write nbytes."""
+    ms = ctypes.c_double()
+    check(load().cmf_stream_copy(int(nbytes), int(reps), ctypes.byref(ms)))
+    return ms.value

@@ -10,6 +10,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -108,20 +110,23 @@ struct cmf_lattice {
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t N = 0;
-  int64_t pstride = 0;
   void *buf[2] = {nullptr, nullptr};
   int parity = 0;  // buf[parity] holds the state of the current step
   double *partials = nullptr;
+  double *level2 = nullptr;
   int nparts = 0;
+  int partials_cap = 0;
+  int cus = 256;
   double *series = nullptr;
   int cap = 0;
   int64_t *step_dev = nullptr;
   int64_t read_step = 0;   // first step whose statistics were not returned
-  int64_t host_step = 0;   // steps enqueued so far
   int block = 256;
   int grid = 1;
   double lambda[27];
   double w[27];
+  double amp[27];
+  float scale[27];
   double mass0 = 0.0;
   StepParams<float> pf;
   StepParams<double> pd;
@@ -141,7 +146,6 @@ void fill_step_params(const cmf_lattice *L, const double *amp,
   p.nxb = (L->desc.nx + L->block - 1) / L->block;
   p.ntiles = p.nxb * p.ny * p.nz;
   p.noise = L->desc.kT > 0.0 ? 1 : 0;
-  p.pstride = L->pstride;
   p.rho0 = (R)L->desc.rho0;
   for (int v = 0; v < L->q; ++v) {
     p.amp[v] = (R)amp[v];
@@ -157,6 +161,92 @@ void fill_step_params(const cmf_lattice *L, const double *amp,
   p.replica = L->desc.replica;
 }
 
+// tuned launch shapes of this process, keyed by device/lattice/storage/box
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tuned;
+bool g_tune_file_loaded = false;
+
+std::string tune_key(const cmf_lattice *L) {
+  char b[160];
+  snprintf(b, sizeof b, "dev%d:q%d:s%d:g%d:%dx%dx%d", L->device, L->q, L->storage,
+           L->general ? 1 : 0, L->desc.nx, L->desc.ny, L->desc.nz);
+  return b;
+}
+
+void load_tune_file_locked() {
+  if (g_tune_file_loaded) return;
+  g_tune_file_loaded = true;
+  const char *path = getenv("CMFLB_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char key[160];
+  int block, grid;
+  double ms;
+  while (fscanf(f, "%159s %d %d %lf", key, &block, &grid, &ms) == 4) g_tuned[key] = {block, grid};
+  fclose(f);
+}
+
+void remember_tuned(const cmf_lattice *L, int block, int grid, double ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
+  const std::string key = tune_key(L);
+  g_tuned[key] = {block, grid};
+  const char *path = getenv("CMFLB_TUNE_CACHE");
+  if (path && *path) {
+    FILE *f = fopen(path, "a");
+    if (f) {
+      fprintf(f, "%s %d %d %.6f\n", key.c_str(), block, grid, ms);
+      fclose(f);
+    }
+  }
+}
+
+bool lookup_tuned(const cmf_lattice *L, int *block, int *grid) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tuned.find(tune_key(L));
+  if (it == g_tuned.end()) return false;
+  *block = it->second.first;
+  *grid = it->second.second;
+  return true;
+}
+
+int default_block(int nx) { return nx >= 192 ? 256 : ((nx + 63) / 64) * 64; }
+
+int ntiles_for(const cmf_lattice *L, int block) {
+  return ((L->desc.nx + block - 1) / block) * L->desc.ny * L->desc.nz;
+}
+
+void drop_graphs(cmf_lattice *L) {
+  for (int k = 0; k < 2; ++k)
+    if (L->graph[k]) {
+      (void)hipGraphExecDestroy(L->graph[k]);
+      L->graph[k] = nullptr;
+    }
+}
+
+// Apply a launch shape: step parameters, partials capacity, graphs.
+int apply_launch(cmf_lattice *L, int block, int grid, const double *amp,
+                 const float *scale) {
+  L->block = block;
+  fill_step_params(L, amp, scale, L->pd);
+  fill_step_params(L, amp, scale, L->pf);
+  const int nt = L->pf.ntiles;
+  L->grid = grid < nt ? grid : nt;
+  L->nparts = L->grid;
+  if (L->nparts > L->partials_cap) {
+    if (L->partials) (void)hipFree(L->partials);
+    L->partials = nullptr;
+    L->partials_cap = 0;
+    if (hipMalloc((void **)&L->partials, sizeof(double) * kPartStride * L->nparts) != hipSuccess)
+      return fail(CMF_ENOMEM, "hipMalloc of the statistics partials failed");
+    L->partials_cap = L->nparts;
+  }
+  drop_graphs(L);
+  return CMF_OK;
+}
+
 const void *step_params(const cmf_lattice *L) {
   return L->storage == kF64 ? (const void *)&L->pd : (const void *)&L->pf;
 }
@@ -166,10 +256,30 @@ int enqueue_one_step(cmf_lattice *L) {
   void *dst = L->buf[1 - L->parity];
   HIP_TRY(launch_step(L->q, L->storage, L->general, step_params(L), src, dst,
                       L->step_dev, L->partials, L->grid, L->block, L->stream));
-  HIP_TRY(launch_finalize(L->partials, L->nparts, L->series, L->cap,
+  HIP_TRY(launch_finalize(L->partials, L->nparts, L->level2, L->series, L->cap,
                           L->step_dev, L->mass0,
                           !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream));
   L->parity ^= 1;
+  return CMF_OK;
+}
+
+// Time n full steps (fused step + statistics finalize) as direct launches.
+int time_full_steps(cmf_lattice *L, int n, double *ms_out) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, L->stream);
+  int rc = CMF_OK;
+  for (int s = 0; s < n && e == hipSuccess && rc == CMF_OK; ++s) rc = enqueue_one_step(L);
+  if (e == hipSuccess) e = hipEventRecord(e1, L->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc != CMF_OK) return rc;
+  if (e != hipSuccess) return fail(CMF_EHIP, "timing failed: %s", hipGetErrorString(e));
+  *ms_out = ms;
   return CMF_OK;
 }
 
@@ -203,6 +313,7 @@ void release(cmf_lattice *L) {
     if (L->buf[k]) (void)hipFree(L->buf[k]);
   }
   if (L->partials) (void)hipFree(L->partials);
+  if (L->level2) (void)hipFree(L->level2);
   if (L->series) (void)hipFree(L->series);
   if (L->step_dev) (void)hipFree(L->step_dev);
   if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
@@ -254,7 +365,6 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
   L->q = desc->q;
   L->storage = desc->storage;
   L->N = (int64_t)desc->nx * desc->ny * desc->nz;
-  L->pstride = (L->N + 127) / 128 * 128;
   L->cap = desc->series_capacity > 0 ? desc->series_capacity : 4096;
   const int q = L->q;
 
@@ -287,24 +397,14 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
     }
   }
   L->mass0 = (double)L->N * desc->rho0;
-
-  // launch geometry: tiles of BX sites along x, persistent-style grid
-  const int bx_env = env_int("CMF_BLOCK", 0);
-  int bx = desc->nx >= 192 ? 256 : ((desc->nx + 63) / 64) * 64;
-  if (bx_env == 64 || bx_env == 128 || bx_env == 192 || bx_env == 256) bx = bx_env;
-  L->block = bx;
-  fill_step_params(L, amp, scale, L->pd);
-  fill_step_params(L, amp, scale, L->pf);
-  const int ntiles = L->pf.ntiles;
-  int grid = env_int("CMF_GRID", 0);
-  if (grid <= 0) grid = 2048;
-  L->grid = grid < ntiles ? grid : ntiles;
-  L->nparts = L->grid;
+  for (int v = 0; v < q; ++v) {
+    L->amp[v] = amp[v];
+    L->scale[v] = scale[v];
+  }
 
   L->cp.nx = desc->nx;
   L->cp.ny = desc->ny;
   L->cp.nz = desc->nz;
-  L->cp.pstride = L->pstride;
   L->cp.rho0 = desc->rho0;
   for (int i = 0; i < q; ++i) {
     L->cp.w[i] = L->w[i];
@@ -327,18 +427,37 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
     }
     L->own_stream = true;
   }
-  const size_t bytes = (size_t)q * L->pstride * storage_bytes(L->storage);
+  const size_t bytes = ((size_t)q * L->N * storage_bytes(L->storage) + 255) / 256 * 256;
   for (int k = 0; k < 2; ++k) {
     if (hipMalloc(&L->buf[k], bytes) != hipSuccess) {
       release(L);
       return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
   }
-  if (hipMalloc((void **)&L->partials, sizeof(double) * kPartStride * L->nparts) != hipSuccess ||
-      hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
+  if (hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
+      hipMalloc((void **)&L->level2, sizeof(double) * kPartStride * kMaxLevel2) != hipSuccess ||
       hipMalloc((void **)&L->step_dev, sizeof(int64_t)) != hipSuccess) {
     release(L);
     return fail(CMF_ENOMEM, "hipMalloc of statistics buffers failed");
+  }
+  // launch shape: a tuned one for this key if known, else the defaults
+  // (persistent grid of 2 x CUs for 4- and 8-byte storage, 16 x CUs for
+  // 16-bit storage, which is issue-bound and wants more waves)
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, L->device) == hipSuccess && prop.multiProcessorCount > 0)
+      L->cus = prop.multiProcessorCount;
+    int block = default_block(desc->nx);
+    int grid = (storage_bytes(L->storage) >= 4 ? 2 : 16) * L->cus;
+    lookup_tuned(L, &block, &grid);
+    const int be = env_int("CMF_BLOCK", 0), ge = env_int("CMF_GRID", 0);
+    if (be == 64 || be == 128 || be == 192 || be == 256) block = be;
+    if (ge > 0) grid = ge;
+    rc = apply_launch(L, block, grid, L->amp, L->scale);
+    if (rc != CMF_OK) {
+      release(L);
+      return rc;
+    }
   }
   *out = L;
   rc = cmf_init_equilibrium(L, nullptr, nullptr);
@@ -383,7 +502,6 @@ int cmf_init_equilibrium(cmf_lattice *L, const double *rho, const double *u) {
   if (du) (void)hipFree(du);
   if (e != hipSuccess) return fail(CMF_EHIP, "equilibrium initialisation failed: %s", hipGetErrorString(e));
   L->read_step = 0;
-  L->host_step = 0;
   return CMF_OK;
 }
 
@@ -459,7 +577,6 @@ int cmf_step(cmf_lattice *L, int64_t nsteps) {
     int rc = enqueue_one_step(L);
     if (rc != CMF_OK) return rc;
   }
-  L->host_step += nsteps;
   return CMF_OK;
 }
 
@@ -480,7 +597,7 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
                       L->partials, L->grid, L->block, L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
     if (e == hipSuccess)
-      e = launch_finalize(L->partials, L->nparts, L->series, L->cap, L->step_dev, L->mass0,
+      e = launch_finalize(L->partials, L->nparts, L->level2, L->series, L->cap, L->step_dev, L->mass0,
                           !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream);
     if (e != hipSuccess) rc = fail(CMF_EHIP, "profiled step failed: %s", hipGetErrorString(e));
     L->parity ^= 1;
@@ -495,9 +612,105 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
     total += ms;
   }
   for (auto &x : ev) (void)hipEventDestroy(x);
-  L->host_step += nsteps;
   *kernel_ms = total;
   return rc;
+}
+
+int cmf_get_launch(cmf_lattice *L, cmf_launch *out) {
+  if (!L || !out) return fail(CMF_EINVAL, "NULL argument");
+  out->block = L->block;
+  out->grid = L->grid;
+  out->ms_per_step = 0.0;
+  return CMF_OK;
+}
+
+int cmf_set_launch(cmf_lattice *L, int32_t block, int32_t grid) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (!(block == 64 || block == 128 || block == 192 || block == 256))
+    return fail(CMF_EINVAL, "block must be 64, 128, 192 or 256, got %d", block);
+  if (grid < 1) return fail(CMF_EINVAL, "grid must be >= 1, got %d", grid);
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  return apply_launch(L, block, grid, L->amp, L->scale);
+}
+
+int cmf_autotune(cmf_lattice *L, int32_t steps_per_trial, cmf_launch *trials, int32_t cap,
+                 int32_t *n_out) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (steps_per_trial < 1) return fail(CMF_EINVAL, "steps_per_trial must be >= 1");
+  if (n_out) *n_out = 0;
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  // snapshot: current population buffer, step counter, series ring
+  const size_t bytes = ((size_t)L->q * L->N * storage_bytes(L->storage) + 255) / 256 * 256;
+  void *saved = nullptr;
+  double *saved_series = nullptr;
+  if (hipMalloc(&saved, bytes) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  if (hipMalloc((void **)&saved_series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess) {
+    (void)hipFree(saved);
+    return fail(CMF_ENOMEM, "hipMalloc of the statistics snapshot failed");
+  }
+  int64_t step0 = 0;
+  const int parity0 = L->parity;
+  const int block0 = L->block, grid0 = L->grid;
+  hipError_t e = hipMemcpyAsync(saved, L->buf[parity0], bytes, hipMemcpyDeviceToDevice, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(saved_series, L->series, sizeof(double) * kSeriesStride * L->cap,
+                       hipMemcpyDeviceToDevice, L->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&step0, L->step_dev, sizeof(int64_t), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(saved);
+    (void)hipFree(saved_series);
+    return fail(CMF_EHIP, "autotune snapshot failed: %s", hipGetErrorString(e));
+  }
+  std::vector<int> blocks;
+  for (int b = 64; b <= 256; b += 64)
+    if (b == 64 || b - 64 < L->desc.nx) blocks.push_back(b);
+  std::vector<cmf_launch> done;
+  int rc = CMF_OK;
+  for (int b : blocks) {
+    std::vector<int> grids;
+    for (int m : {1, 2, 4, 8, 16, 32}) grids.push_back(m * L->cus);
+    grids.push_back(ntiles_for(L, b));
+    int last = -1;
+    for (int g : grids) {
+      const int gg = g < ntiles_for(L, b) ? g : ntiles_for(L, b);
+      if (gg == last) continue;
+      last = gg;
+      rc = apply_launch(L, b, gg, L->amp, L->scale);
+      if (rc != CMF_OK) break;
+      double warm = 0.0, ms = 0.0;
+      rc = time_full_steps(L, 1, &warm);
+      if (rc == CMF_OK) rc = time_full_steps(L, steps_per_trial, &ms);
+      if (rc != CMF_OK) break;
+      done.push_back(cmf_launch{b, gg, ms / steps_per_trial});
+    }
+    if (rc != CMF_OK) break;
+  }
+  // restore the state exactly
+  L->parity = parity0;
+  e = hipMemcpyAsync(L->buf[parity0], saved, bytes, hipMemcpyDeviceToDevice, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(L->series, saved_series, sizeof(double) * kSeriesStride * L->cap,
+                       hipMemcpyDeviceToDevice, L->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(L->step_dev, &step0, sizeof(int64_t), hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(saved);
+  (void)hipFree(saved_series);
+  if (rc == CMF_OK && e != hipSuccess) rc = fail(CMF_EHIP, "autotune restore failed: %s", hipGetErrorString(e));
+  if (rc != CMF_OK) {
+    (void)apply_launch(L, block0, grid0, L->amp, L->scale);
+    return rc;
+  }
+  size_t best = 0;
+  for (size_t k = 1; k < done.size(); ++k)
+    if (done[k].ms_per_step < done[best].ms_per_step) best = k;
+  rc = apply_launch(L, done[best].block, done[best].grid, L->amp, L->scale);
+  if (rc != CMF_OK) return rc;
+  remember_tuned(L, done[best].block, done[best].grid, done[best].ms_per_step);
+  if (trials)
+    for (size_t k = 0; k < done.size() && (int32_t)k < cap; ++k) trials[k] = done[k];
+  if (n_out) *n_out = (int32_t)done.size();
+  return CMF_OK;
 }
 
 int cmf_synchronize(cmf_lattice *L) {
@@ -594,6 +807,38 @@ int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key
   (void)hipFree(dc);
   (void)hipFree(dout);
   if (e != hipSuccess) return fail(CMF_EHIP, "philox_words failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_stream_copy(size_t bytes, int32_t reps, double *best_ms) {
+  if (!best_ms || reps < 1 || bytes == 0) return fail(CMF_EINVAL, "bad arguments");
+  const size_t n16 = (bytes + 15) / 16;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, n16 * 16) != hipSuccess || hipMalloc(&b, n16 * 16) != hipSuccess) {
+    if (a) (void)hipFree(a);
+    return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", n16 * 16);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemset(a, 0, n16 * 16);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_stream_copy(a, b, n16, nullptr);  // warm-up
+  double best = 1e30;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = launch_stream_copy(a, b, n16, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best) best = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (e != hipSuccess) return fail(CMF_EHIP, "stream copy failed: %s", hipGetErrorString(e));
+  *best_ms = best;
   return CMF_OK;
 }
 

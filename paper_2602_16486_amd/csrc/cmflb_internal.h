@@ -11,6 +11,10 @@ constexpr int kNAcc = 11;      // accumulated statistics per block
 constexpr int kPartStride = 12;// doubles per block partial
 constexpr int kSeriesStride = 12;
 constexpr int kMaxBlock = 256;
+// statistics partials beyond this count are first summed by up to
+// kMaxLevel2 workgroups (second-level rows)
+constexpr int kLevel2Threshold = 1024;
+constexpr int kMaxLevel2 = 256;
 
 // Parameters of one lattice as the step kernels see them (kernel argument,
 // so every field lives in scalar registers).
@@ -19,7 +23,6 @@ struct StepParams {
   int32_t nx, ny, nz, nxb;  // box and x-tiles per row
   int32_t ntiles;           // nxb * ny * nz
   int32_t noise;            // kT > 0
-  int64_t pstride;          // elements between population planes
   R rho0;
   R amp[27];   // I~_v sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2)
   R oml[27];   // 1 - Lambda_v
@@ -31,7 +34,6 @@ struct StepParams {
 // Parameters of the state conversion kernels (FP64 always).
 struct ConvParams {
   int32_t nx, ny, nz;
-  int64_t pstride;
   double rho0;
   double w[27];
   float scale[27], iscale[27];
@@ -44,9 +46,9 @@ hipError_t launch_step(int q, int storage, bool general, const void *params,
                        const void *src, void *dst, const int64_t *step_ptr,
                        double *partials, int grid, int block,
                        hipStream_t stream);
-hipError_t launch_finalize(const double *partials, int nparts, double *series,
-                           int cap, int64_t *step_ptr, double mass0,
-                           bool stats, hipStream_t stream);
+hipError_t launch_finalize(const double *partials, int nparts, double *level2,
+                           double *series, int cap, int64_t *step_ptr,
+                           double mass0, bool stats, hipStream_t stream);
 hipError_t launch_init_eq(int q, int storage, const ConvParams &cp,
                           const double *rho, const double *u, void *buf,
                           hipStream_t stream);
@@ -66,5 +68,7 @@ hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
                          uint32_t key1, uint32_t *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
+hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
+                              hipStream_t stream);
 
 }  // namespace cmf

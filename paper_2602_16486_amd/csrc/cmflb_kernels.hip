@@ -9,9 +9,9 @@
 // central moments, collision (eq. cm_collision with phi of eq. phi_general),
 // back transformation f* = T(u)^-1 k*, streaming (eq. streaming).
 //
-// Memory layout: populations are structure-of-arrays, one plane of
-// `pstride` elements per population, site s = x + nx (y + ny z) inside a
-// plane, stored as deviations d_i = f_i - w_i rho0.  The buffer of step t
+// Memory layout: populations are stored as deviations d_i = f_i - w_i rho0
+// in a row-interleaved structure of arrays (pop_row_offset): for lattice row
+// (y, z) the Q rows of nx values are contiguous.  The buffer of step t
 // holds post-collision values of step t - 1 at their source site; step t
 // pulls d_i(x - c_i), collides, and writes d*_i(x) to the other buffer
 // (two-buffer pull scheme).  Every value is read once and written once per
@@ -50,17 +50,46 @@ __device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
                                              uint32_t site, uint32_t step,
                                              Acc &acc) {
   constexpr int Q = L::Q;
-  // step 1: rho = rho0 + sum d, rho u = sum c d (eq. macro)
+  // step 1: rho = rho0 + sum d, rho u = sum c d (eq. macro).  D3Q27 forms
+  // them from per-row partial sums (sum and difference along x of each
+  // (c_y, c_z) row, then along y), which also yields the off-diagonal sums
+  // sxy, sxz, syz of the pre-collision k_7..k_9.
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  R sxy = R(0), sxz = R(0), syz = R(0);
+  if constexpr (Q == 27) {
+    constexpr PosTable<L> tab{};
+    R s0[9], s1[9];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += d[i];
-    if (L::cx[i] > 0) jx += d[i];
-    if (L::cx[i] < 0) jx -= d[i];
-    if (L::cy[i] > 0) jy += d[i];
-    if (L::cy[i] < 0) jy -= d[i];
-    if (L::cz[i] > 0) jz += d[i];
-    if (L::cz[i] < 0) jz -= d[i];
+    for (int r = 0; r < 9; ++r) {
+      const R gm = d[tab.pop[3 * r]], g0 = d[tab.pop[3 * r + 1]],
+              gp = d[tab.pop[3 * r + 2]];
+      s0[r] = (gm + gp) + g0;  // sum over c_x
+      s1[r] = gp - gm;         // sum of c_x d
+    }
+    R t0[3], t1[3], u0[3], v1[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+      t0[z] = (s0[3 * z] + s0[3 * z + 2]) + s0[3 * z + 1];
+      t1[z] = s0[3 * z + 2] - s0[3 * z];
+      u0[z] = (s1[3 * z] + s1[3 * z + 2]) + s1[3 * z + 1];
+      v1[z] = s1[3 * z + 2] - s1[3 * z];
+    }
+    drho = (t0[0] + t0[2]) + t0[1];
+    jx = (u0[0] + u0[2]) + u0[1];
+    jy = (t1[0] + t1[2]) + t1[1];
+    jz = t0[2] - t0[0];
+    sxy = (v1[0] + v1[2]) + v1[1];
+    sxz = u0[2] - u0[0];
+    syz = t1[2] - t1[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      drho += d[i];
+      if (L::cx[i] > 0) jx += d[i];
+      if (L::cx[i] < 0) jx -= d[i];
+      if (L::cy[i] > 0) jy += d[i];
+      if (L::cy[i] < 0) jy -= d[i];
+    }
   }
   const R rho = p.rho0 + drho;
   const R irho = R(1) / rho;
@@ -94,18 +123,6 @@ __device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
     // need their pre-collision value; every other noisy mode is pure noise
     // around k_eq = 0.
     if constexpr (Q == 27) {
-      R sxy = R(0), sxz = R(0), syz = R(0);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int pxy = L::cx[i] * L::cy[i], pxz = L::cx[i] * L::cz[i],
-                  pyz = L::cy[i] * L::cz[i];
-        if (pxy > 0) sxy += d[i];
-        if (pxy < 0) sxy -= d[i];
-        if (pxz > 0) sxz += d[i];
-        if (pxz < 0) sxz -= d[i];
-        if (pyz > 0) syz += d[i];
-        if (pyz < 0) syz -= d[i];
-      }
       // k_7, k_8, k_9 (Sec. 2.3): sum f c_a c_b - rho u_a u_b; the rest
       // weights do not contribute to the off-diagonal sums.
       const R k7 = sxy - jx * uy, k8 = sxz - jx * uz, k9 = syz - jy * uz;
@@ -123,7 +140,7 @@ __device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
         t[L::mode_pos[v]] = val;
       }
     } else {
-      R sd = R(0), sxy = R(0);
+      R sd = R(0);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int dd = L::cx[i] * L::cx[i] - L::cy[i] * L::cy[i];
@@ -199,8 +216,12 @@ __device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
       t[8] = ks[8];
     }
   }
-  // steps 5-6: d* = T(u)^-1 (k* - rho0 G(u))
+  // steps 5-6: d* = T(u)^-1 (k* - rho0 G(u)).  The zeroth entry is
+  // k*_0 - rho0 = rho - rho0 = drho exactly (mode 0 is conserved); it is set
+  // directly rather than as (rho0 + drho) - rho0, which would round drho to
+  // the spacing of FP32 numbers near rho0.
   add_rest_moments<L::D, R>(t, -p.rho0, ux, uy, uz);
+  t[0] = drho;
   {
     const Axis<R> ax(ux), ay(uy), az(uz);
     tensor_inv<L::D, R>(t, ax, ay, az);
@@ -242,93 +263,146 @@ __device__ __forceinline__ int wrap_sub(int a, int c, int n) {
   return r;
 }
 
+// Pull the Q populations of site (x, y, z): f_i(x) <- f*_i(x - c_i).  The
+// row part of every address is wave-uniform (scalar registers); only the x
+// offset (with its periodic wrap) is per lane.
+template <class L, typename S, typename R>
+__device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
+                                          const StepParams<R> &p, int x, int y,
+                                          int z) {
+  using ST = Store<S, R>;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1), (uint32_t)x,
+                          (uint32_t)(x == 0 ? nx - 1 : x - 1)};
+  int64_t srow[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int ys = wrap_sub(y, a - 1, ny);
+      const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+      srow[a][b] = (int64_t)ys + (int64_t)ny * zs;
+    }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
+    d[i] = ST::load(base + xs[L::cx[i] + 1], p.scale[i]);
+  }
+}
+
+template <class L, typename S, typename R>
+__device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
+                                           const StepParams<R> &p, int x,
+                                           int64_t row) {
+  using ST = Store<S, R>;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    S *base = dst + pop_row_offset<L::Q>(i, row, p.nx);
+    ST::store(base + (uint32_t)x, d[i], p.iscale[i]);
+  }
+}
+
+struct TileXY {
+  int x, y, z;
+};
+
+__device__ __forceinline__ TileXY tile_coords(int tile, int nxb, int ny, int bx) {
+  const int xb = tile % nxb;
+  const int row = tile / nxb;
+  return TileXY{xb * bx + (int)threadIdx.x, row % ny, row / ny};
+}
+
 template <class L, typename S, typename R, bool GENERAL>
 __global__ __launch_bounds__(kMaxBlock) void k_step(
     const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
     const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
   constexpr int Q = L::Q;
-  using ST = Store<S, R>;
   const uint32_t step = (uint32_t)*step_ptr;
   const int BX = blockDim.x;
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int nx = p.nx, ny = p.ny;
   Acc acc;
 #pragma unroll
   for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
 
   for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
-    const int xb = tile % p.nxb;
-    const int row = tile / p.nxb;
-    const int y = row % ny;
-    const int z = row / ny;
-    const int x = xb * BX + (int)threadIdx.x;
-    if (x < nx) {
-      // source offsets of the pull f_i(x) <- f*_i(x - c_i)
-      const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
-      int rowoff[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          const int ys = wrap_sub(y, a - 1, ny);
-          const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
-          rowoff[a][b] = (ys + ny * zs) * nx;
-        }
+    const TileXY c = tile_coords(tile, p.nxb, ny, BX);
+    if (c.x < nx) {
       R d[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int off = rowoff[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1];
-        d[i] = ST::load(src + (int64_t)i * p.pstride + off, p.scale[i]);
-      }
-      const int site = x + nx * (y + ny * z);
+      load_site<L, S, R>(d, src, p, c.x, c.y, c.z);
+      const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
+      const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL>(d, p, (uint32_t)site, step, acc);
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        ST::store(dst + (int64_t)i * p.pstride + site, d[i], p.iscale[i]);
+      store_site<L, S, R>(d, dst, p, c.x, row);
     }
   }
   block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride);
 }
 
 // ---------------------------------------------------------------------------
-// statistics finalize: fixed-order FP64 sum of the block partials into the
-// series row of the current step, then advance the step counter
+// statistics finalize: fixed-order FP64 sums of the block partials (in two
+// levels when there are many blocks) into the series row of the current
+// step, then advance the step counter
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(
-    const double *__restrict__ partials, int nparts, double *__restrict__ series,
-    int cap, int64_t *__restrict__ step_ptr, double mass0, int stats) {
+__device__ __forceinline__ void block_sum_rows(const double *__restrict__ rows,
+                                               int lo, int hi, double *out) {
   __shared__ double sh[256][kNAcc];
   const int tid = threadIdx.x;
+  double s[kNAcc];
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) s[k] = 0.0;
+  for (int b = lo + tid; b < hi; b += 256)
+#pragma unroll
+    for (int k = 0; k < kNAcc; ++k) s[k] += rows[(int64_t)b * kPartStride + k];
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) sh[tid][k] = s[k];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h)
+#pragma unroll
+      for (int k = 0; k < kNAcc; ++k) sh[tid][k] += sh[tid + h][k];
+    __syncthreads();
+  }
+  if (tid < kNAcc) out[tid] = sh[0][tid];
+}
+
+// first level: block r sums partial rows [r chunk, (r + 1) chunk)
+__global__ __launch_bounds__(256) void k_reduce_partials(
+    const double *__restrict__ partials, int nparts, int chunk,
+    double *__restrict__ level2) {
+  const int lo = blockIdx.x * chunk;
+  const int hi = lo + chunk < nparts ? lo + chunk : nparts;
+  block_sum_rows(partials, lo, hi, level2 + (int64_t)blockIdx.x * kPartStride);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(
+    const double *__restrict__ rows, int nrows, double *__restrict__ series,
+    int cap, int64_t *__restrict__ step_ptr, double mass0, int stats) {
+  __shared__ double tot[kNAcc];
   const int64_t step = *step_ptr;
   if (stats) {
-    double s[kNAcc];
-#pragma unroll
-    for (int k = 0; k < kNAcc; ++k) s[k] = 0.0;
-    for (int b = tid; b < nparts; b += 256)
-#pragma unroll
-      for (int k = 0; k < kNAcc; ++k) s[k] += partials[(int64_t)b * kPartStride + k];
-#pragma unroll
-    for (int k = 0; k < kNAcc; ++k) sh[tid][k] = s[k];
+    block_sum_rows(rows, 0, nrows, tot);
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (tid < h)
-#pragma unroll
-        for (int k = 0; k < kNAcc; ++k) sh[tid][k] += sh[tid + h][k];
-      __syncthreads();
-    }
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
       double *row = series + (step % cap) * kSeriesStride;
       row[0] = (double)step;
-      row[1] = mass0 + sh[0][0];
+      row[1] = mass0 + tot[0];
 #pragma unroll
-      for (int k = 1; k < kNAcc; ++k) row[1 + k] = sh[0][k];
+      for (int k = 1; k < kNAcc; ++k) row[1 + k] = tot[k];
     }
   }
-  if (tid == 0) *step_ptr = step + 1;
+  if (threadIdx.x == 0) *step_ptr = step + 1;
 }
 
 // ---------------------------------------------------------------------------
 // state conversion kernels (FP64 arithmetic)
 // ---------------------------------------------------------------------------
+// element offset of population i at site s in the population buffer
+template <int Q>
+__device__ __forceinline__ int64_t pop_site_offset(const ConvParams &cp, int i,
+                                                   int64_t s) {
+  return pop_row_offset<Q>(i, s / cp.nx, cp.nx) + s % cp.nx;
+}
+
 template <class L>
 __device__ __forceinline__ int64_t shifted_site(const ConvParams &cp, int64_t s,
                                                 int i, int sign) {
@@ -366,7 +440,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const ConvParams cp,
   tensor_inv<L::D, double>(t, ax, ay, az);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    ST::store(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+    ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
               t[pop_pos<L>(i)], cp.iscale[i]);
 }
 
@@ -380,7 +454,7 @@ __global__ __launch_bounds__(256) void k_set_state(const ConvParams cp,
   if (s >= N) return;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    ST::store(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+    ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
               f[(int64_t)i * N + s] - cp.w[i] * cp.rho0, cp.iscale[i]);
 }
 
@@ -396,7 +470,7 @@ __global__ __launch_bounds__(256) void k_get_state(const ConvParams cp,
   for (int i = 0; i < L::Q; ++i)
     f[(int64_t)i * N + s] =
         cp.w[i] * cp.rho0 +
-        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
                  cp.scale[i]);
 }
 
@@ -414,7 +488,7 @@ __global__ __launch_bounds__(256) void k_gather(const ConvParams cp,
   for (int i = 0; i < L::Q; ++i)
     out[k * L::Q + i] =
         cp.w[i] * cp.rho0 +
-        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
                  cp.scale[i]);
 }
 
@@ -431,7 +505,7 @@ __global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const double d =
-        ST::load(buf + (int64_t)i * cp.pstride + shifted_site<L>(cp, s, i, -1),
+        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
                  cp.scale[i]);
     drho += d;
     j[0] += L::cx[i] * d;
@@ -473,6 +547,15 @@ __global__ __launch_bounds__(256) void k_philox(const uint32_t *__restrict__ ctr
   out[4 * k + 1] = w.y;
   out[4 * k + 2] = w.z;
   out[4 * k + 3] = w.w;
+}
+
+// plain streaming copy of n16 16-byte elements (the HBM calibration kernel)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void cmf_stream_copy_kernel(
+    const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 __global__ void k_zero_i64(int64_t *p, int64_t n) {
@@ -545,10 +628,24 @@ hipError_t launch_step(int q, int storage, bool general, const void *params,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const double *partials, int nparts, double *series,
-                           int cap, int64_t *step_ptr, double mass0, bool stats,
-                           hipStream_t stream) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, partials, nparts,
+hipError_t launch_finalize(const double *partials, int nparts, double *level2,
+                           double *series, int cap, int64_t *step_ptr,
+                           double mass0, bool stats, hipStream_t stream) {
+  const double *rows = partials;
+  int nrows = nparts;
+  if (stats && nparts > kLevel2Threshold) {
+    int nb = (nparts + kLevel2Threshold - 1) / kLevel2Threshold;
+    if (nb > kMaxLevel2) nb = kMaxLevel2;
+    const int chunk = (nparts + nb - 1) / nb;
+    nb = (nparts + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, stream, partials,
+                       nparts, chunk, level2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rows = level2;
+    nrows = nb;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, rows, nrows,
                      series, cap, step_ptr, mass0, stats ? 1 : 0);
   return hipGetLastError();
 }
@@ -668,6 +765,19 @@ hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, stream,
                      ctr, n, key0, key1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
+                              hipStream_t stream) {
+  if (n16 == 0) return hipSuccess;
+  // one 16-byte element per thread (a grid-stride loop only beyond 2^30
+  // workgroups): the fastest plain copy measured on gfx950
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > ((size_t)1 << 30)) blocks = (size_t)1 << 30;
+  hipLaunchKernelGGL(cmf_stream_copy_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     stream, static_cast<const u32x4 *>(src),
+                     static_cast<u32x4 *>(dst), n16);
   return hipGetLastError();
 }
 

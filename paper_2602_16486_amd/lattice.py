@@ -100,6 +100,26 @@ class Lattice:
         _lib.check(self._lib.cmf_profile_steps(self._h, int(n), ctypes.byref(ms)))
         return ms.value
 
+    # -- launch shape -------------------------------------------------------
+    @property
+    def launch(self):
+        """(block, grid) of the fused-step kernel."""
+        out = _lib.Launch()
+        _lib.check(self._lib.cmf_get_launch(self._h, ctypes.byref(out)))
+        return out.block, out.grid
+
+    def set_launch(self, block, grid):
+        _lib.check(self._lib.cmf_set_launch(self._h, int(block), int(grid)))
+
+    def autotune(self, steps_per_trial=10):
+        """Time the candidate launch shapes (state restored afterwards), keep
+        the fastest; returns a list of (block, grid, ms_per_step)."""
+        cap = 64
+        buf = (_lib.Launch * cap)()
+        n = ctypes.c_int32()
+        _lib.check(self._lib.cmf_autotune(self._h, int(steps_per_trial), buf, cap, ctypes.byref(n)))
+        return [(buf[k].block, buf[k].grid, buf[k].ms_per_step) for k in range(min(n.value, cap))]
+
     def synchronize(self):
         _lib.check(self._lib.cmf_synchronize(self._h))
 

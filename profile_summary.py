@@ -1,0 +1,133 @@
+#!/usr/bin/env python3
+"""Summarise the rocprofv3 runs of bench.py into profiles/.
+
+Inputs (written by rocprofv3 under a results directory):
+  <dir>/prof_trace/trace_kernel_stats.csv        (--kernel-trace --stats)
+  <dir>/prof_fetch/fetch_counter_collection.csv  (--pmc FETCH_SIZE)
+  <dir>/prof_write/write_counter_collection.csv  (--pmc WRITE_SIZE)
+  <dir>/prof_trace.json                          (bench.py's JSON line of the trace run)
+
+The HBM byte counters are calibrated with the plain copy kernel that
+bench.py runs (cmf_stream_copy_kernel, which reads and writes exactly
+27 * 256^3 * 4 bytes): factor = known bytes / counter reading, per counter.
+
+Outputs: profiles/k_step_d3q27_f32_256cube.md (the summary) and
+profiles/k_step_d3q27_f32_256cube.counters.json (read by bench.py, tied to
+the kernel sources' hash and the launch shape).
+
+    python profile_summary.py gpurun_out
+"""
+import csv
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402  (kernel_source_hash, constants)
+
+STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false>"
+COPY_KERNEL = "cmf::cmf_stream_copy_kernel"
+N = 256 ** 3
+ALG_BYTES = 2 * 27 * 4 * N
+COPY_BYTES = 27 * N * 4  # per direction
+
+CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv "
+             "-- python3 bench.py --steps 50 --warmup 32 --variants \"\" --no-cpu --no-tune")
+CMD_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv "
+             "-- python3 bench.py --steps 10 --warmup 32 --variants \"\" --no-cpu --no-tune")
+CMD_WRITE = CMD_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("prof_fetch", "prof_write").replace(
+    "-o fetch", "-o write")
+
+
+def _median_counter(path, kernel):
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if r["Kernel_Name"].startswith(kernel)]
+    return statistics.median(vals), len(vals)
+
+
+def main(outdir):
+    stats = {r["Name"]: r for r in csv.DictReader(open(os.path.join(outdir, "prof_trace", "trace_kernel_stats.csv")))}
+    step = next(v for k, v in stats.items() if k.startswith(STEP_KERNEL))
+    copy = next(v for k, v in stats.items() if k.startswith(COPY_KERNEL))
+    fetch_step, nf = _median_counter(os.path.join(outdir, "prof_fetch", "fetch_counter_collection.csv"), STEP_KERNEL)
+    fetch_copy, _ = _median_counter(os.path.join(outdir, "prof_fetch", "fetch_counter_collection.csv"), COPY_KERNEL)
+    write_step, nw = _median_counter(os.path.join(outdir, "prof_write", "write_counter_collection.csv"), STEP_KERNEL)
+    write_copy, _ = _median_counter(os.path.join(outdir, "prof_write", "write_counter_collection.csv"), COPY_KERNEL)
+    bench_line = json.loads(open(os.path.join(outdir, "prof_trace.json")).read().strip().splitlines()[-1])
+    launch = bench_line["config"]["launch"]
+    f_fetch = COPY_BYTES / (fetch_copy * 1024)
+    f_write = COPY_BYTES / (write_copy * 1024)
+    read_b = fetch_step * 1024 * f_fetch
+    write_b = write_step * 1024 * f_write
+    traffic = read_b + write_b
+    avg_ns = float(step["AverageNs"])
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            for r in csv.DictReader(open(os.path.join(outdir, "prof_trace", "trace_kernel_trace.csv")))
+            if r["Kernel_Name"].startswith(STEP_KERNEL)]
+    med_ns = statistics.median(durs)
+    rec = {
+        "kernel": STEP_KERNEL, "workload": bench_line["config"]["workload"], "launch": launch,
+        "source_sha256": bench.kernel_source_hash(),
+        "fetch_kib_per_dispatch": fetch_step, "write_kib_per_dispatch": write_step,
+        "fetch_factor": f_fetch, "write_factor": f_write,
+        "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
+        "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": ALG_BYTES,
+        "traffic_over_algorithmic": traffic / ALG_BYTES,
+        "rocprof_avg_ns": avg_ns, "rocprof_median_ns": med_ns,
+        "bench_kernel_ms": bench_line["roofline"]["kernel_ms"],
+    }
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "k_step_d3q27_f32_256cube.counters.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [
+        "# k_step<D3Q27, f32> on D3Q27 256^3 (bench workload) — rocprofv3 summary",
+        "",
+        "Workload: " + bench_line["config"]["workload"] + f"; launch (block, grid) = {tuple(launch)}.",
+        "",
+        "Commands (run from the repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`;",
+        "the three runs share one tuning cache, `CMFLB_TUNE_CACHE=gpurun_out/tune.txt`, written by a",
+        "preceding `python bench.py`):",
+        "",
+        "    " + CMD_TRACE,
+        "    " + CMD_FETCH,
+        "    " + CMD_WRITE,
+        "    python profile_summary.py gpurun_out",
+        "",
+        "## Kernel trace (--kernel-trace --stats)",
+        "",
+        "| kernel | calls | average ns | min ns | max ns |",
+        "|---|---|---|---|---|",
+    ]
+    for k, v in sorted(stats.items(), key=lambda kv: -float(kv[1]["TotalDurationNs"])):
+        lines.append(f"| `{k[:90]}` | {v['Calls']} | {float(v['AverageNs']):.0f} | {v['MinNs']} | {v['MaxNs']} |")
+    lines += [
+        "",
+        f"Step kernel: {avg_ns / 1e6:.4f} ms average, {med_ns / 1e6:.4f} ms median over {len(durs)} dispatches; "
+        f"bench.py's live HIP-event measurement of the same kernel: {bench_line['roofline']['kernel_ms']:.4f} ms.",
+        f"Achieved (algorithmic {ALG_BYTES} B per launch = 216 B/site x 256^3, median duration): "
+        f"{ALG_BYTES / (med_ns * 1e-9) / 1e9:.0f} GB/s = {ALG_BYTES / (med_ns * 1e-9) / 8e12:.3f} of 8 TB/s.",
+        f"Plain copy kernel: {float(copy['AverageNs']) / 1e6:.4f} ms for 2 x {COPY_BYTES} B = "
+        f"{2 * COPY_BYTES / (float(copy['AverageNs']) * 1e-9) / 1e9:.0f} GB/s.",
+        "",
+        "## HBM bytes (--pmc FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median)",
+        "",
+        "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---|---|---|",
+        f"| step ({nf}/{nw} dispatches) | {fetch_step:.0f} | {write_step:.0f} |",
+        f"| plain copy (known {COPY_BYTES // 1024} KiB each way) | {fetch_copy:.0f} | {write_copy:.0f} |",
+        "",
+        f"Calibration factors (known bytes / counter): FETCH x{f_fetch:.4f}, WRITE x{f_write:.4f}.",
+        f"Step kernel traffic per launch: read {read_b / 1e9:.3f} GB + write {write_b / 1e9:.3f} GB = "
+        f"{traffic / 1e9:.3f} GB, {traffic / ALG_BYTES:.3f} x the algorithmic {ALG_BYTES / 1e9:.3f} GB "
+        f"(reads {read_b / (ALG_BYTES / 2):.3f} x, writes {write_b / (ALG_BYTES / 2):.3f} x).",
+        "",
+    ]
+    with open(os.path.join(ROOT, "profiles", "k_step_d3q27_f32_256cube.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")

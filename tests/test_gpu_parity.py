@@ -82,7 +82,7 @@ def test_init_equilibrium_matches_oracle(q, shape, storage):
         got = lat.get_populations()
         assert lat.step_index == 0
     ref = O.init_equilibrium(q, n, rho=rho, u=u)
-    tol = 1e-15 if storage == "f64" else 1e-7
+    tol = 1e-13 if storage == "f64" else 1e-7
     assert _rel_err(got, ref, q) < tol
 
 
@@ -101,9 +101,10 @@ def test_set_get_roundtrip(q, shape, storage):
         assert np.array_equal(got, f)
     else:
         rel = {"f32": 2 ** -24, "f16": 2 ** -11, "bf16": 2 ** -8}[storage]
-        # rounding is relative to the deviation, not to f (plus the FP16
-        # subnormal spacing 2^-24 s_i, below 1e-10 for these scales)
-        assert np.all(np.abs(got - f) <= rel * np.abs(dev) * 1.0001 + 1e-10)
+        # rounding is relative to the deviation, not to f: FP32 then the
+        # 16-bit format (at most rel (1 + 2^-13)), plus the FP16 subnormal
+        # spacing 2^-24 s_i (s_i <= 2^-6 here)
+        assert np.all(np.abs(got - f) <= rel * np.abs(dev) * (1 + 2 ** -12) + 2 ** -30)
     assert np.array_equal(g, got[:, sites].T)
 
 
@@ -158,7 +159,9 @@ def test_config1_prefix_matches_oracle(storage):
     assert np.array_equal(st[:, 0], np.arange(steps))
     rtol = 1e-10 if storage == "f64" else 50 * F32_TOL(steps)
     assert np.allclose(st[:, 8:10], ref[:, 8:10], rtol=rtol, atol=1e-14)
-    assert np.abs(st[:, 1] - ref[:, 1]).max() < 1e-9
+    # mass: FP64 exact to rounding; FP32 rounds each stored deviation
+    # (~1e-10 per site and step), a random walk over N sites and the steps
+    assert np.abs(st[:, 1] - ref[:, 1]).max() < (1e-9 if storage == "f64" else 2e-6)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -208,21 +211,50 @@ def test_graph_replay_equals_direct_launches():
     assert np.array_equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("grid,block", [("1", "64"), ("7", "128"), ("100000", "256")])
-def test_results_do_not_depend_on_launch_shape(monkeypatch, grid, block):
+@pytest.mark.parametrize("block,grid", [(64, 1), (128, 7), (192, 3), (256, 100000)])
+def test_results_do_not_depend_on_launch_shape(block, grid):
     q, shape = 27, (150, 7, 5)
     f0 = _random_state(q, shape, 43)
     with Lattice(q, shape, storage="f32", kT=1e-4, seed=3) as lat:
         lat.set_populations(f0)
         lat.step(5)
         ref = lat.get_populations()
-    monkeypatch.setenv("CMF_GRID", grid)
-    monkeypatch.setenv("CMF_BLOCK", block)
+        ref_st = lat.stats()
     with Lattice(q, shape, storage="f32", kT=1e-4, seed=3) as lat:
+        lat.set_launch(block, grid)
+        assert lat.launch[0] == block
         lat.set_populations(f0)
         lat.step(5)
         got = lat.get_populations()
+        st = lat.stats()
     assert np.array_equal(got, ref)
+    # statistics agree up to the FP64 summation order
+    assert np.allclose(st, ref_st, rtol=1e-12, atol=1e-18)
+
+
+def test_autotune_restores_state_and_keeps_results():
+    q, shape = 27, (200, 16, 12)
+    f0 = _random_state(q, shape, 45)
+    with Lattice(q, shape, storage="f32", kT=1e-4, seed=3) as lat:
+        lat.set_populations(f0)
+        lat.step(3)
+        ref = lat.get_populations()
+        trials = lat.autotune(steps_per_trial=2)
+        assert len(trials) >= 4 and all(t[2] > 0 for t in trials)
+        best = min(trials, key=lambda t: t[2])
+        assert lat.launch == best[:2]
+        assert lat.step_index == 3
+        assert np.array_equal(lat.get_populations(), ref)
+        lat.step(4)
+        got = lat.get_populations()
+        st = lat.stats()
+    with Lattice(q, shape, storage="f32", kT=1e-4, seed=3, flags=_lib.FLAG_NO_GRAPH) as lat:
+        lat.set_populations(f0)
+        lat.step(7)
+        assert np.array_equal(lat.get_populations(), got)
+        st2 = lat.stats()
+    assert np.array_equal(st[:, 0], np.arange(7))
+    assert np.allclose(st, st2, rtol=1e-12, atol=1e-18)
 
 
 def test_nonfinite_is_reported():
