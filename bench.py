@@ -106,6 +106,63 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True):
     }
 
 
+def ensemble_run(steps, warmup, stream, torch, eq_steps=1000):
+    """Config 5: 256 D2Q9 replicas (edges uniform in [32, 512] per axis) and
+    64 D3Q27 replicas (edges uniform in [32, 96]), each with its own seed,
+    kT log-uniform in [1e-6, 1e-3] and tau uniform in [0.502, 2.0], FP32,
+    one launch per step; compared with the same replicas stepped one
+    lattice at a time (same kernels, separate launches)."""
+    import numpy as np
+    from paper_2602_16486_amd import Ensemble, Lattice
+    from paper_2602_16486_amd import workloads as W
+    manifest = W.ensemble_manifest()
+    total = sum(W.n_sites(r["shape"]) for r in manifest)
+    with Ensemble(manifest, storage="f32", stream=stream.cuda_stream, series_capacity=4096) as ens:
+        ens.step(warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ens.step(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        kernel_ms = ens.profile_steps(10) / 10
+        # equipartition per replica over the second half of eq_steps steps
+        ens.step(eq_steps - (steps + warmup + 10) % eq_steps)
+        ratios = []
+        for k, r in enumerate(manifest):
+            st = ens.stats(k)
+            n = W.n_sites(r["shape"])
+            half = st[len(st) // 2:]
+            dims = 2 if r["q"] == 9 else 3
+            ratios.append(float(half[:, 8:8 + dims].sum(axis=1).mean() / (dims * n) * r["rho0"] / r["kT"]))
+    # the same replicas one at a time
+    seq_ms = 0.0
+    nseq = 20
+    for r in manifest:
+        with Lattice(r["q"], r["shape"], storage="f32", tau=r["tau"], kT=r["kT"], seed=r["seed"],
+                     replica=r["replica"], stream=stream.cuda_stream) as lat:
+            lat.step(2)
+            torch.cuda.synchronize()
+            a.record(stream)
+            lat.step(nseq)
+            b.record(stream)
+            torch.cuda.synchronize()
+            seq_ms += a.elapsed_time(b) / nseq
+    ratios = np.array(ratios)
+    return {
+        "value": total / (ms * 1e-3) / 1e9, "unit": "GLUPS", "ms_per_step": ms,
+        "kernel_ms": kernel_ms, "sites": total, "replicas": len(manifest),
+        "bytes_per_step": sum(W.n_sites(r["shape"]) * 2 * r["q"] * 4 for r in manifest),
+        "sequential_single_replica_glups": total / (seq_ms * 1e-3) / 1e9,
+        "speedup_vs_sequential": seq_ms / ms,
+        "u2_over_kT_median": float(np.median(ratios)),
+        "u2_over_kT_p05_p95": [float(np.percentile(ratios, 5)), float(np.percentile(ratios, 95))],
+        "equipartition_window": f"steps {eq_steps // 2}-{eq_steps}",
+    }
+
+
 def cpu_baseline():
     """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 40 steps
     from rest (same parameters as the GPU workload)."""
@@ -131,6 +188,7 @@ def main():
     ap.add_argument("--variants", default="f16,bf16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -207,6 +265,12 @@ def main():
         "u2_over_kT": main_run["u2_over_kT"],
         "variants": variants,
     }
+    if not args.no_ensemble:
+        log("timing the batched ensemble (256 D2Q9 + 64 D3Q27 replicas)")
+        ens = ensemble_run(min(args.steps, 200), 40, stream, torch)
+        ens["achieved_gbs"] = ens["bytes_per_step"] / (ens["kernel_ms"] * 1e-3) / 1e9
+        result["ensemble"] = ens
+        log(f"ensemble: {ens['value']:.2f} GLUPS ({ens['speedup_vs_sequential']:.2f}x the sequential runs)")
     if not args.no_cpu:
         log("timing the CPU oracle sample")
         result["cpu_baseline"] = cpu_baseline()

@@ -222,6 +222,62 @@ int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step,
 int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0,
                      uint32_t key1, uint32_t *out);
 
+/* ---- batched ensembles ------------------------------------------------
+ * Many independent replicas (D2Q9 and D3Q27 mixed; uneven boxes; each with
+ * its own tau / rates, kT, rho0, seed and replica number) advanced together
+ * by ONE fused-step launch per step that covers the tiles of every replica,
+ * followed by a per-replica statistics reduction; runs of steps are
+ * replayed from captured HIP graphs unless CMF_FLAG_NO_GRAPH.  Each replica
+ * evolves exactly as a cmf_lattice created from the same descriptor would
+ * (same arithmetic, same noise keys).  All replicas share the storage type
+ * and the flags of descs[0] and one step counter. */
+typedef struct cmf_ensemble cmf_ensemble;
+
+/* Create an ensemble of n >= 1 replicas from n descriptors (validated as in
+ * cmf_create; storage and flags must agree; series_capacity of descs[0]
+ * applies to all).  All replicas start at rest at step 0.  Allocates two
+ * population arenas holding every replica, the replica records, the tile
+ * map and the statistics buffers.  Errors: CMF_EINVAL, CMF_ENOMEM,
+ * CMF_EHIP. */
+int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream,
+                        cmf_ensemble **out);
+
+/* Release the ensemble (synchronises its stream). */
+int cmf_ensemble_destroy(cmf_ensemble *ens);
+
+/* Number of replicas, total sites and tiles (any output may be NULL). */
+int cmf_ensemble_info(cmf_ensemble *ens, int32_t *n_replicas,
+                      int64_t *total_sites, int64_t *n_tiles);
+
+/* Replica `index` (creation order) to f_eq(rho, u), with the arguments of
+ * cmf_init_equilibrium.  The shared step counter is not changed.
+ * Synchronous. */
+int cmf_ensemble_init_equilibrium(cmf_ensemble *ens, int32_t index,
+                                  const double *rho, const double *u);
+
+/* Pre-collision populations of replica `index` (q x N host doubles, as in
+ * cmf_set_populations / cmf_get_populations).  Synchronous. */
+int cmf_ensemble_set_populations(cmf_ensemble *ens, int32_t index,
+                                 const double *f);
+int cmf_ensemble_get_populations(cmf_ensemble *ens, int32_t index, double *f);
+
+/* Enqueue nsteps steps of every replica.  Asynchronous. */
+int cmf_ensemble_step(cmf_ensemble *ens, int64_t nsteps);
+
+/* nsteps direct-launch steps with a HIP event pair around every ensemble
+ * step kernel; *kernel_ms = summed kernel time.  Synchronous. */
+int cmf_ensemble_profile_steps(cmf_ensemble *ens, int64_t nsteps,
+                               double *kernel_ms);
+
+/* Wait for the ensemble's stream; index of the next step. */
+int cmf_ensemble_synchronize(cmf_ensemble *ens);
+int cmf_ensemble_get_step(cmf_ensemble *ens, int64_t *step);
+
+/* Statistics rows of replica `index` since the previous call for that
+ * replica, as cmf_stats. */
+int cmf_ensemble_stats(cmf_ensemble *ens, int32_t index, cmf_moments *out,
+                       int64_t cap, int64_t *n_out);
+
 /* Diagnostic: practical HBM ceiling.  Allocates two device buffers of
  * `bytes` bytes (rounded up to 16), copies one into the other `reps` times
  * with a plain streaming copy kernel (`cmf_stream_copy_kernel`, 16-byte

@@ -110,6 +110,23 @@ def load():
     lib.cmf_get_launch.argtypes = [vp, ctypes.POINTER(Launch)]
     lib.cmf_set_launch.argtypes = [vp, i32, i32]
     lib.cmf_autotune.argtypes = [vp, i32, ctypes.POINTER(Launch), i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.cmf_ensemble_create.argtypes = [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]
+    lib.cmf_ensemble_destroy.argtypes = [vp]
+    lib.cmf_ensemble_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_ensemble_init_equilibrium.argtypes = [vp, i32, _dp, _dp]
+    lib.cmf_ensemble_set_populations.argtypes = [vp, i32, _dp]
+    lib.cmf_ensemble_get_populations.argtypes = [vp, i32, _dp]
+    lib.cmf_ensemble_step.argtypes = [vp, i64]
+    lib.cmf_ensemble_profile_steps.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.cmf_ensemble_synchronize.argtypes = [vp]
+    lib.cmf_ensemble_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_ensemble_stats.argtypes = [vp, i32, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
+    for name in ("cmf_ensemble_create", "cmf_ensemble_destroy", "cmf_ensemble_info",
+                 "cmf_ensemble_init_equilibrium", "cmf_ensemble_set_populations",
+                 "cmf_ensemble_get_populations", "cmf_ensemble_step", "cmf_ensemble_profile_steps",
+                 "cmf_ensemble_synchronize", "cmf_ensemble_get_step", "cmf_ensemble_stats"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("cmf_get_launch", "cmf_set_launch", "cmf_autotune", "cmf_stream_copy", "cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
                  "cmf_get_populations", "cmf_gather_sites", "cmf_step", "cmf_synchronize",
                  "cmf_get_step", "cmf_stats", "cmf_sample_macro", "cmf_noise_sample",
@@ -129,6 +146,27 @@ def declared_functions(header=HEADER):
     """Names of the functions declared in include/cmflb.h."""
     text = open(header).read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(cmf_\w+)\s*\(", text, re.M)))
+
+
+def make_desc(q, shape, storage="f32", rho0=1.0, tau=0.8, kT=0.0, lam=None, seed=1, replica=0,
+              flags=0, series_capacity=0):
+    """A Desc plus the numpy array that keeps its rate vector alive."""
+    nx, ny, nz = (tuple(int(s) for s in shape) + (1, 1))[:3]
+    d = Desc()
+    d.q, d.nx, d.ny, d.nz = int(q), nx, ny, nz
+    d.storage = STORAGE[storage]
+    d.flags = flags
+    d.rho0, d.tau, d.kT = float(rho0), float(tau), float(kT)
+    keep = None
+    if lam is not None:
+        keep = np.ascontiguousarray(lam, dtype=np.float64)
+        if keep.shape != (int(q),):
+            raise ValueError(f"lam must have {q} entries")
+        d.lam = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.seed = int(seed)
+    d.replica = int(replica)
+    d.series_capacity = int(series_capacity)
+    return d, keep
 
 
 def _d(a):

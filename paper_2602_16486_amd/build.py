@@ -30,6 +30,10 @@ def compile_flags():
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed FP32 instructions are disabled on purpose for every kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # multiply-adds fused only within a source expression: every kernel
+        # that inlines the collision (single lattice, ensemble) then rounds
+        # identically, so replicas are bit-identical to standalone lattices
+        "-ffp-contract=on",
         "-Wall", "-Wno-unused-function",
         "-I", os.path.join(ROOT, "include"),
     ]

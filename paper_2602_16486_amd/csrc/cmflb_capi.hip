@@ -101,6 +101,45 @@ int env_int(const char *name, int dflt) {
 
 }  // namespace
 
+namespace {
+
+// FP64 per-mode constants of one descriptor: rates, weights, noise
+// amplitudes (eq. phi_general without the local sqrt(rho)), storage scales.
+struct ModeConstants {
+  double lambda[27], w[27], amp[27];
+  float scale[27];
+  bool general;
+};
+
+void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
+  const int q = desc->q;
+  const double omega = 1.0 / desc->tau;
+  for (int v = 0; v < q; ++v)
+    mc.lambda[v] = desc->lambda ? desc->lambda[v] : (is_omega_mode(q, v) ? omega : 1.0);
+  mc.general = false;
+  for (int v = first_noisy(q); v < q; ++v)
+    if (!is_omega_mode(q, v) && mc.lambda[v] != 1.0) mc.general = true;
+  if (env_int("CMF_FORCE_GENERAL", 0)) mc.general = true;
+  double b[27];
+  if (q == 9) lattice_weights<D2Q9>(mc.w); else lattice_weights<D3Q27>(mc.w);
+  mode_norms(q, b);
+  for (int v = 0; v < q; ++v) {
+    const double lv = mc.lambda[v];
+    mc.amp[v] = v >= first_noisy(q) ? sqrt(desc->kT * lv * (2.0 - lv) * b[v] / kCs2) : 0.0;
+  }
+  for (int i = 0; i < q; ++i) {
+    if (desc->storage == kF16 || desc->storage == kBF16) {
+      const double sigma = desc->kT > 0.0 ? sqrt(desc->rho0 * desc->kT * mc.w[i] / kCs2)
+                                          : 1e-2 * mc.w[i];
+      mc.scale[i] = (float)ldexp(1.0, (int)ceil(log2(sigma)));
+    } else {
+      mc.scale[i] = 1.0f;
+    }
+  }
+}
+
+}  // namespace
+
 struct cmf_lattice {
   cmf_desc desc;
   int q = 0;
@@ -368,33 +407,18 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
   L->cap = desc->series_capacity > 0 ? desc->series_capacity : 4096;
   const int q = L->q;
 
-  // rates: the paper's pattern unless given
-  const double omega = 1.0 / desc->tau;
-  for (int v = 0; v < q; ++v)
-    L->lambda[v] = desc->lambda ? desc->lambda[v] : (is_omega_mode(q, v) ? omega : 1.0);
-  L->general = false;
-  for (int v = first_noisy(q); v < q; ++v)
-    if (!is_omega_mode(q, v) && L->lambda[v] != 1.0) L->general = true;
-  if (env_int("CMF_FORCE_GENERAL", 0)) L->general = true;
-
-  // FP64 constants: weights, norms, noise amplitudes (eq. phi_general
-  // without the local sqrt(rho)), storage scales
-  double b[27], amp[27];
+  // rates (the paper's pattern unless given) and the FP64 per-mode
+  // constants
+  ModeConstants mc;
+  mode_constants(desc, mc);
+  L->general = mc.general;
+  double amp[27];
   float scale[27];
-  if (q == 9) lattice_weights<D2Q9>(L->w); else lattice_weights<D3Q27>(L->w);
-  mode_norms(q, b);
   for (int v = 0; v < q; ++v) {
-    const double lv = L->lambda[v];
-    amp[v] = v >= first_noisy(q) ? sqrt(desc->kT * lv * (2.0 - lv) * b[v] / kCs2) : 0.0;
-  }
-  for (int i = 0; i < q; ++i) {
-    if (L->storage == kF16 || L->storage == kBF16) {
-      double sigma = desc->kT > 0.0 ? sqrt(desc->rho0 * desc->kT * L->w[i] / kCs2)
-                                    : 1e-2 * L->w[i];
-      scale[i] = (float)ldexp(1.0, (int)ceil(log2(sigma)));
-    } else {
-      scale[i] = 1.0f;
-    }
+    L->lambda[v] = mc.lambda[v];
+    L->w[v] = mc.w[v];
+    amp[v] = mc.amp[v];
+    scale[v] = mc.scale[v];
   }
   L->mass0 = (double)L->N * desc->rho0;
   for (int v = 0; v < q; ++v) {
@@ -839,6 +863,413 @@ int cmf_stream_copy(size_t bytes, int32_t reps, double *best_ms) {
   (void)hipFree(b);
   if (e != hipSuccess) return fail(CMF_EHIP, "stream copy failed: %s", hipGetErrorString(e));
   *best_ms = best;
+  return CMF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batched ensembles
+// ===========================================================================
+struct cmf_ensemble {
+  struct Rep {
+    cmf_desc desc;
+    int64_t N = 0;
+    int64_t offset = 0;  // elements
+    int tile0 = 0, ntiles = 0;
+    ConvParams cp;
+  };
+  int n = 0;
+  int storage = 1;
+  uint32_t flags = 0;
+  bool general = false;
+  bool own_stream = false;
+  hipStream_t stream = nullptr;
+  std::vector<Rep> reps;
+  void *arena[2] = {nullptr, nullptr};
+  size_t arena_bytes = 0;
+  int parity = 0;
+  void *d_reps = nullptr;
+  int32_t *d_tile_rep = nullptr;
+  int ntiles = 0;
+  int64_t total_sites = 0;
+  double *partials = nullptr;
+  double *series = nullptr;
+  double *d_mass0 = nullptr;
+  int cap = 4096;
+  int64_t *step_dev = nullptr;
+  std::vector<int64_t> read_step;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+template <typename R>
+void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble::Rep &rp,
+                  ReplicaParams<R> &p) {
+  memset(&p, 0, sizeof p);
+  p.q = d.q;
+  p.nx = d.nx;
+  p.ny = d.ny;
+  p.nz = d.nz;
+  p.nsites = (int32_t)rp.N;
+  p.tile0 = rp.tile0;
+  p.ntiles = rp.ntiles;
+  p.noise = d.kT > 0.0 ? 1 : 0;
+  p.offset = rp.offset;
+  p.key0 = (uint32_t)d.seed;
+  p.key1 = (uint32_t)(d.seed >> 32);
+  p.replica = d.replica;
+  p.rho0 = (R)d.rho0;
+  for (int v = 0; v < d.q; ++v) {
+    p.amp[v] = (R)mc.amp[v];
+    p.oml[v] = (R)(1.0 - mc.lambda[v]);
+    p.lam[v] = (R)mc.lambda[v];
+    p.scale[v] = mc.scale[v];
+    p.iscale[v] = 1.0f / mc.scale[v];
+  }
+}
+
+void ens_release(cmf_ensemble *E) {
+  if (!E) return;
+  if (E->stream) (void)hipStreamSynchronize(E->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (E->graph[k]) (void)hipGraphExecDestroy(E->graph[k]);
+    if (E->arena[k]) (void)hipFree(E->arena[k]);
+  }
+  if (E->d_reps) (void)hipFree(E->d_reps);
+  if (E->d_tile_rep) (void)hipFree(E->d_tile_rep);
+  if (E->partials) (void)hipFree(E->partials);
+  if (E->series) (void)hipFree(E->series);
+  if (E->d_mass0) (void)hipFree(E->d_mass0);
+  if (E->step_dev) (void)hipFree(E->step_dev);
+  if (E->own_stream && E->stream) (void)hipStreamDestroy(E->stream);
+  delete E;
+}
+
+int ens_enqueue_step(cmf_ensemble *E) {
+  HIP_TRY(launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
+                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
+                               E->partials, E->stream));
+  HIP_TRY(launch_ensemble_finalize(E->storage, E->d_reps, E->n, E->partials, E->series, E->cap,
+                                   E->step_dev, E->d_mass0, !(E->flags & CMF_FLAG_NO_STATS),
+                                   E->stream));
+  E->parity ^= 1;
+  return CMF_OK;
+}
+
+int ens_capture(cmf_ensemble *E, int parity) {
+  const int saved = E->parity;
+  E->parity = parity;
+  HIP_TRY(hipStreamBeginCapture(E->stream, hipStreamCaptureModeThreadLocal));
+  int rc = CMF_OK;
+  for (int s = 0; s < kGraphSteps && rc == CMF_OK; ++s) rc = ens_enqueue_step(E);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(E->stream, &g);
+  E->parity = saved;
+  if (rc != CMF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(CMF_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&E->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(CMF_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int ens_check_index(cmf_ensemble *E, int32_t index) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (index < 0 || index >= E->n) return fail(CMF_EINVAL, "replica index %d outside [0, %d)", index, E->n);
+  return CMF_OK;
+}
+
+void *ens_replica_buffer(cmf_ensemble *E, int index) {
+  return (char *)E->arena[E->parity] + E->reps[index].offset * storage_bytes(E->storage);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_ensemble **out) {
+  if (!out) return fail(CMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || n < 1) return fail(CMF_EINVAL, "need at least one descriptor");
+  for (int r = 0; r < n; ++r) {
+    int rc = validate(&descs[r]);
+    if (rc != CMF_OK) return fail(rc, "replica %d: %s", r, g_last_error.c_str());
+    if (descs[r].storage != descs[0].storage) return fail(CMF_EINVAL, "replica %d: storage differs from replica 0", r);
+    if (descs[r].flags != descs[0].flags) return fail(CMF_EINVAL, "replica %d: flags differ from replica 0", r);
+  }
+  cmf_ensemble *E = new cmf_ensemble();
+  E->n = n;
+  E->storage = descs[0].storage;
+  E->flags = descs[0].flags;
+  E->cap = descs[0].series_capacity > 0 ? descs[0].series_capacity : 4096;
+  E->reps.resize(n);
+  E->read_step.assign(n, 0);
+  std::vector<ModeConstants> mcs(n);
+  int64_t offset = 0;
+  for (int r = 0; r < n; ++r) {
+    cmf_ensemble::Rep &rp = E->reps[r];
+    rp.desc = descs[r];
+    rp.desc.lambda = nullptr;
+    rp.N = (int64_t)descs[r].nx * descs[r].ny * descs[r].nz;
+    rp.offset = offset;
+    offset += ((int64_t)descs[r].q * rp.N + 63) / 64 * 64;
+    mode_constants(&descs[r], mcs[r]);
+    if (mcs[r].general) E->general = true;
+    rp.cp.nx = descs[r].nx;
+    rp.cp.ny = descs[r].ny;
+    rp.cp.nz = descs[r].nz;
+    rp.cp.rho0 = descs[r].rho0;
+    for (int i = 0; i < descs[r].q; ++i) {
+      rp.cp.w[i] = mcs[r].w[i];
+      rp.cp.scale[i] = mcs[r].scale[i];
+      rp.cp.iscale[i] = 1.0f / mcs[r].scale[i];
+    }
+    E->total_sites += rp.N;
+  }
+  // tiles: D3Q27 replicas first, then D2Q9, each in creation order
+  std::vector<int32_t> tile_rep;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int r = 0; r < n; ++r) {
+      if ((pass == 0) != (descs[r].q == 27)) continue;
+      cmf_ensemble::Rep &rp = E->reps[r];
+      rp.tile0 = (int)tile_rep.size();
+      rp.ntiles = (int)((rp.N + kEnsembleBlock - 1) / kEnsembleBlock);
+      if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31)) {
+        ens_release(E);
+        return fail(CMF_EINVAL, "ensemble has too many tiles");
+      }
+      tile_rep.insert(tile_rep.end(), rp.ntiles, r);
+    }
+  E->ntiles = (int)tile_rep.size();
+  E->arena_bytes = ((size_t)offset * storage_bytes(E->storage) + 255) / 256 * 256;
+  hipError_t e = hip_stream ? hipSuccess : hipStreamCreate(&E->stream);
+  if (hip_stream) E->stream = (hipStream_t)hip_stream; else E->own_stream = true;
+  if (e != hipSuccess) {
+    ens_release(E);
+    return fail(CMF_EHIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
+  }
+  const size_t rec = E->storage == kF64 ? sizeof(ReplicaParams<double>) : sizeof(ReplicaParams<float>);
+  bool ok = hipMalloc(&E->arena[0], E->arena_bytes) == hipSuccess &&
+            hipMalloc(&E->arena[1], E->arena_bytes) == hipSuccess &&
+            hipMalloc(&E->d_reps, rec * n) == hipSuccess &&
+            hipMalloc((void **)&E->d_tile_rep, sizeof(int32_t) * E->ntiles) == hipSuccess &&
+            hipMalloc((void **)&E->partials, sizeof(double) * kPartStride * E->ntiles) == hipSuccess &&
+            hipMalloc((void **)&E->series, sizeof(double) * kSeriesStride * E->cap * n) == hipSuccess &&
+            hipMalloc((void **)&E->d_mass0, sizeof(double) * n) == hipSuccess &&
+            hipMalloc((void **)&E->step_dev, sizeof(int64_t)) == hipSuccess;
+  if (!ok) {
+    ens_release(E);
+    return fail(CMF_ENOMEM, "ensemble allocation (%zu bytes per arena) failed", E->arena_bytes);
+  }
+  std::vector<double> mass0(n);
+  for (int r = 0; r < n; ++r) mass0[r] = (double)E->reps[r].N * descs[r].rho0;
+  if (E->storage == kF64) {
+    std::vector<ReplicaParams<double>> h(n);
+    for (int r = 0; r < n; ++r) fill_replica(descs[r], mcs[r], E->reps[r], h[r]);
+    e = hipMemcpy(E->d_reps, h.data(), rec * n, hipMemcpyHostToDevice);
+  } else {
+    std::vector<ReplicaParams<float>> h(n);
+    for (int r = 0; r < n; ++r) fill_replica(descs[r], mcs[r], E->reps[r], h[r]);
+    e = hipMemcpy(E->d_reps, h.data(), rec * n, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(E->d_tile_rep, tile_rep.data(), sizeof(int32_t) * E->ntiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(E->d_mass0, mass0.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  // at rest every deviation is exactly zero
+  if (e == hipSuccess) e = hipMemsetAsync(E->arena[0], 0, E->arena_bytes, E->stream);
+  if (e == hipSuccess) e = launch_zero_i64(E->step_dev, 1, E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  if (e != hipSuccess) {
+    ens_release(E);
+    return fail(CMF_EHIP, "ensemble initialisation failed: %s", hipGetErrorString(e));
+  }
+  *out = E;
+  return CMF_OK;
+}
+
+int cmf_ensemble_destroy(cmf_ensemble *E) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  ens_release(E);
+  return CMF_OK;
+}
+
+int cmf_ensemble_info(cmf_ensemble *E, int32_t *n_replicas, int64_t *total_sites, int64_t *n_tiles) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (n_replicas) *n_replicas = E->n;
+  if (total_sites) *total_sites = E->total_sites;
+  if (n_tiles) *n_tiles = E->ntiles;
+  return CMF_OK;
+}
+
+int cmf_ensemble_init_equilibrium(cmf_ensemble *E, int32_t index, const double *rho, const double *u) {
+  int rc = ens_check_index(E, index);
+  if (rc != CMF_OK) return rc;
+  cmf_ensemble::Rep &rp = E->reps[index];
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  const int64_t N = rp.N;
+  double *drho = nullptr, *du = nullptr;
+  if (rho)
+    for (int64_t s = 0; s < N; ++s)
+      if (!(rho[s] > 0.0) || !isfinite(rho[s]))
+        return fail(CMF_EINVAL, "rho[%lld] = %g is not a positive density", (long long)s, rho[s]);
+  hipError_t e = hipSuccess;
+  if (rho) {
+    e = hipMalloc((void **)&drho, sizeof(double) * N);
+    if (e == hipSuccess) e = hipMemcpy(drho, rho, sizeof(double) * N, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && u) {
+    e = hipMalloc((void **)&du, sizeof(double) * 3 * N);
+    if (e == hipSuccess) e = hipMemcpy(du, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess)
+    e = launch_init_eq(rp.desc.q, E->storage, rp.cp, drho, du, ens_replica_buffer(E, index), E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  if (drho) (void)hipFree(drho);
+  if (du) (void)hipFree(du);
+  if (e != hipSuccess) return fail(CMF_EHIP, "ensemble init failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_ensemble_set_populations(cmf_ensemble *E, int32_t index, const double *f) {
+  int rc = ens_check_index(E, index);
+  if (rc != CMF_OK) return rc;
+  if (!f) return fail(CMF_EINVAL, "f is NULL");
+  cmf_ensemble::Rep &rp = E->reps[index];
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  const size_t bytes = sizeof(double) * rp.desc.q * rp.N;
+  double *df = nullptr;
+  if (hipMalloc((void **)&df, bytes) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  hipError_t e = hipMemcpy(df, f, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_set_state(rp.desc.q, E->storage, rp.cp, df, ens_replica_buffer(E, index), E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  (void)hipFree(df);
+  if (e != hipSuccess) return fail(CMF_EHIP, "ensemble set_populations failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_ensemble_get_populations(cmf_ensemble *E, int32_t index, double *f) {
+  int rc = ens_check_index(E, index);
+  if (rc != CMF_OK) return rc;
+  if (!f) return fail(CMF_EINVAL, "f is NULL");
+  cmf_ensemble::Rep &rp = E->reps[index];
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  const size_t bytes = sizeof(double) * rp.desc.q * rp.N;
+  double *df = nullptr;
+  if (hipMalloc((void **)&df, bytes) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  hipError_t e = launch_get_state(rp.desc.q, E->storage, rp.cp, ens_replica_buffer(E, index), df, E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  if (e == hipSuccess) e = hipMemcpy(f, df, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(df);
+  if (e != hipSuccess) return fail(CMF_EHIP, "ensemble get_populations failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+int cmf_ensemble_step(cmf_ensemble *E, int64_t nsteps) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (nsteps < 0) return fail(CMF_EINVAL, "nsteps < 0");
+  const bool graphs = !(E->flags & CMF_FLAG_NO_GRAPH);
+  int64_t left = nsteps;
+  while (graphs && left >= kGraphSteps) {
+    if (!E->graph[E->parity]) {
+      int rc = ens_capture(E, E->parity);
+      if (rc != CMF_OK) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(E->graph[E->parity], E->stream));
+    left -= kGraphSteps;
+  }
+  for (; left > 0; --left) {
+    int rc = ens_enqueue_step(E);
+    if (rc != CMF_OK) return rc;
+  }
+  return CMF_OK;
+}
+
+int cmf_ensemble_profile_steps(cmf_ensemble *E, int64_t nsteps, double *kernel_ms) {
+  if (!E || !kernel_ms) return fail(CMF_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CMF_EINVAL, "nsteps < 0");
+  *kernel_ms = 0.0;
+  std::vector<hipEvent_t> ev(2 * nsteps, nullptr);
+  for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
+  hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+    e = hipEventRecord(ev[2 * s], E->stream);
+    if (e == hipSuccess)
+      e = launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
+                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
+                               E->partials, E->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], E->stream);
+    if (e == hipSuccess)
+      e = launch_ensemble_finalize(E->storage, E->d_reps, E->n, E->partials, E->series, E->cap,
+                                   E->step_dev, E->d_mass0, !(E->flags & CMF_FLAG_NO_STATS),
+                                   E->stream);
+    E->parity ^= 1;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  double total = 0.0;
+  for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
+    total += ms;
+  }
+  for (auto &x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return fail(CMF_EHIP, "ensemble profiling failed: %s", hipGetErrorString(e));
+  *kernel_ms = total;
+  return CMF_OK;
+}
+
+int cmf_ensemble_synchronize(cmf_ensemble *E) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  return CMF_OK;
+}
+
+int cmf_ensemble_get_step(cmf_ensemble *E, int64_t *step) {
+  if (!E || !step) return fail(CMF_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  HIP_TRY(hipMemcpy(step, E->step_dev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return CMF_OK;
+}
+
+int cmf_ensemble_stats(cmf_ensemble *E, int32_t index, cmf_moments *out, int64_t cap, int64_t *n_out) {
+  int rc = ens_check_index(E, index);
+  if (rc != CMF_OK) return rc;
+  if (!n_out || (cap > 0 && !out)) return fail(CMF_EINVAL, "NULL argument");
+  *n_out = 0;
+  int64_t step = 0;
+  rc = cmf_ensemble_get_step(E, &step);
+  if (rc != CMF_OK) return rc;
+  if (E->flags & CMF_FLAG_NO_STATS) {
+    E->read_step[index] = step;
+    return CMF_OK;
+  }
+  int64_t first = E->read_step[index];
+  if (step - first > E->cap) first = step - E->cap;
+  if (step - first > cap) first = step - cap;
+  std::vector<double> ring((size_t)E->cap * kSeriesStride);
+  if (step > first)
+    HIP_TRY(hipMemcpy(ring.data(), E->series + (size_t)index * E->cap * kSeriesStride,
+                      sizeof(double) * ring.size(), hipMemcpyDeviceToHost));
+  bool bad = false;
+  for (int64_t s = first; s < step; ++s) {
+    const double *r = ring.data() + (s % E->cap) * kSeriesStride;
+    cmf_moments &m = out[s - first];
+    m.step = r[0];
+    m.sum_rho = r[1];
+    for (int a = 0; a < 3; ++a) {
+      m.sum_j[a] = r[2 + a];
+      m.sum_u[a] = r[5 + a];
+      m.sum_u2[a] = r[8 + a];
+    }
+    m.nonfinite = r[11];
+    if (m.nonfinite != 0.0) bad = true;
+  }
+  *n_out = step - first;
+  E->read_step[index] = step;
+  if (bad) return fail(CMF_ENONFINITE, "non-finite density or velocity in a recorded step");
   return CMF_OK;
 }
 

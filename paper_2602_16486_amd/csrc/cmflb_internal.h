@@ -31,6 +31,22 @@ struct StepParams {
   uint32_t key0, key1, replica;
 };
 
+// One replica of a batched ensemble as the ensemble kernel sees it (an
+// array in device memory; every field is read with scalar loads because a
+// workgroup works on one replica).
+template <typename R>
+struct ReplicaParams {
+  int32_t q, nx, ny, nz;
+  int32_t nsites, tile0, ntiles, noise;
+  int64_t offset;  // element offset of the replica's populations in an arena
+  uint32_t key0, key1, replica, pad;
+  R rho0;
+  R amp[27];
+  R oml[27];
+  R lam[27];
+  float scale[27], iscale[27];
+};
+
 // Parameters of the state conversion kernels (FP64 always).
 struct ConvParams {
   int32_t nx, ny, nz;
@@ -70,5 +86,17 @@ hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
                               hipStream_t stream);
+
+// ensemble (cmflb_ensemble.hip)
+constexpr int kEnsembleBlock = 256;
+hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
+                                const int32_t *tile_rep, int ntiles,
+                                const void *src, void *dst,
+                                const int64_t *step_ptr, double *partials,
+                                hipStream_t stream);
+hipError_t launch_ensemble_finalize(int storage, const void *reps, int nrep,
+                                    const double *partials, double *series,
+                                    int cap, int64_t *step_ptr, double *mass0,
+                                    bool stats, hipStream_t stream);
 
 }  // namespace cmf

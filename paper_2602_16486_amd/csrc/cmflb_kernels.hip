@@ -24,6 +24,8 @@
 #include "cmflb_device.h"
 #include "cmflb_internal.h"
 
+#include <type_traits>
+
 namespace cmf {
 
 // ---------------------------------------------------------------------------
@@ -45,8 +47,11 @@ __device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
 // Lambda; otherwise the rates follow the paper's pattern (Lambda = 1 except
 // the modes relaxed at omega: D2Q9 v = 4, 5; D3Q27 v = 7, 8, 9) and only
 // those pre-collision central moments are formed, as the paper does.
-template <class L, typename R, bool GENERAL>
-__device__ __forceinline__ void collide_site(R *d, const StepParams<R> &p,
+// P is any parameter record with the fields of StepParams (rho0, amp, oml,
+// lam, noise, replica, key0, key1): the single-lattice kernel passes its
+// kernel argument, the ensemble kernel a replica record in global memory.
+template <class L, typename R, bool GENERAL, class P>
+__device__ __forceinline__ void collide_site(R *d, const P &p,
                                              uint32_t site, uint32_t step,
                                              Acc &acc) {
   constexpr int Q = L::Q;
@@ -263,15 +268,15 @@ __device__ __forceinline__ int wrap_sub(int a, int c, int n) {
   return r;
 }
 
-// Pull the Q populations of site (x, y, z): f_i(x) <- f*_i(x - c_i).  The
-// row part of every address is wave-uniform (scalar registers); only the x
-// offset (with its periodic wrap) is per lane.
+// Pull the Q populations of site (x, y, z) of a box (nx, ny, nz) whose
+// buffer starts at src: f_i(x) <- f*_i(x - c_i), periodic.  When y and z are
+// wave-uniform (single lattice) the row part of every address is scalar;
+// the ensemble kernel passes per-lane rows.
 template <class L, typename S, typename R>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
-                                          const StepParams<R> &p, int x, int y,
-                                          int z) {
+                                          const float *scale, int nx, int ny,
+                                          int nz, int x, int y, int z) {
   using ST = Store<S, R>;
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
   const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1), (uint32_t)x,
                           (uint32_t)(x == 0 ? nx - 1 : x - 1)};
   int64_t srow[3][3];
@@ -286,19 +291,19 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
-    d[i] = ST::load(base + xs[L::cx[i] + 1], p.scale[i]);
+    d[i] = ST::load(base + xs[L::cx[i] + 1], scale[i]);
   }
 }
 
 template <class L, typename S, typename R>
 __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
-                                           const StepParams<R> &p, int x,
+                                           const float *iscale, int nx, int x,
                                            int64_t row) {
   using ST = Store<S, R>;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    S *base = dst + pop_row_offset<L::Q>(i, row, p.nx);
-    ST::store(base + (uint32_t)x, d[i], p.iscale[i]);
+    S *base = dst + pop_row_offset<L::Q>(i, row, nx);
+    ST::store(base + (uint32_t)x, d[i], iscale[i]);
   }
 }
 
@@ -328,11 +333,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
     const TileXY c = tile_coords(tile, p.nxb, ny, BX);
     if (c.x < nx) {
       R d[Q];
-      load_site<L, S, R>(d, src, p, c.x, c.y, c.z);
+      load_site<L, S, R>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL>(d, p, (uint32_t)site, step, acc);
-      store_site<L, S, R>(d, dst, p, c.x, row);
+      store_site<L, S, R>(d, dst, p.iscale, nx, c.x, row);
     }
   }
   block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride);
@@ -564,6 +569,77 @@ __global__ void k_zero_i64(int64_t *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// batched ensemble: one launch per step over the tiles of every replica
+// ---------------------------------------------------------------------------
+// A tile is kEnsembleBlock consecutive sites (x fastest) of one replica, so
+// every lane of a workgroup is busy whatever the box edges; the replica, and
+// with it the lattice type, is uniform per workgroup.  Replicas are listed
+// D3Q27 first (heavier tiles dispatched first).
+template <class L, typename S, typename R, bool GENERAL>
+__device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
+                                              S *__restrict__ dst,
+                                              const ReplicaParams<R> &p,
+                                              int64_t s, uint32_t step,
+                                              Acc &acc) {
+  const uint32_t nx = (uint32_t)p.nx, ny = (uint32_t)p.ny;
+  const uint32_t us = (uint32_t)s;
+  const uint32_t row = us / nx;
+  const int x = (int)(us - row * nx);
+  const int y = (int)(row % ny);
+  const int z = (int)(row / ny);
+  R d[L::Q];
+  load_site<L, S, R>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
+  collide_site<L, R, GENERAL>(d, p, us, step, acc);
+  store_site<L, S, R>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
+}
+
+template <typename S, typename R, bool GENERAL>
+__global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
+    const S *__restrict__ src, S *__restrict__ dst,
+    const ReplicaParams<R> *__restrict__ reps, const int32_t *__restrict__ tile_rep,
+    const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
+  const int tile = blockIdx.x;
+  const ReplicaParams<R> &p = reps[tile_rep[tile]];
+  const uint32_t step = (uint32_t)*step_ptr;
+  Acc acc;
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
+  const int64_t s = (int64_t)(tile - p.tile0) * kEnsembleBlock + threadIdx.x;
+  if (s < p.nsites) {
+    if (p.q == 27)
+      ensemble_site<D3Q27, S, R, GENERAL>(src, dst, p, s, step, acc);
+    else
+      ensemble_site<D2Q9, S, R, GENERAL>(src, dst, p, s, step, acc);
+  }
+  block_store_acc(acc, partials + (int64_t)tile * kPartStride);
+}
+
+// per-replica fixed-order sum of its tiles' partials into its series row
+template <typename R>
+__global__ __launch_bounds__(256) void k_ensemble_reduce(
+    const ReplicaParams<R> *__restrict__ reps, const double *__restrict__ partials,
+    double *__restrict__ series, int cap, const int64_t *__restrict__ step_ptr,
+    const double *__restrict__ mass0) {
+  __shared__ double tot[kNAcc];
+  const int r = blockIdx.x;
+  const ReplicaParams<R> &p = reps[r];
+  const int64_t step = *step_ptr;
+  block_sum_rows(partials, p.tile0, p.tile0 + p.ntiles, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double *row = series + ((int64_t)r * cap + step % cap) * kSeriesStride;
+    row[0] = (double)step;
+    row[1] = mass0[r] + tot[0];
+#pragma unroll
+    for (int k = 1; k < kNAcc; ++k) row[1 + k] = tot[k];
+  }
+}
+
+__global__ void k_bump_step(int64_t *step_ptr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step_ptr = *step_ptr + 1;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -778,6 +854,56 @@ hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
   hipLaunchKernelGGL(cmf_stream_copy_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      stream, static_cast<const u32x4 *>(src),
                      static_cast<u32x4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
+                                const int32_t *tile_rep, int ntiles,
+                                const void *src, void *dst,
+                                const int64_t *step_ptr, double *partials,
+                                hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  auto go = [&](auto stt, auto rt, auto gt) {
+    using S = typename decltype(stt)::type;
+    using R = typename decltype(rt)::type;
+    constexpr bool G = decltype(gt)::value;
+    hipLaunchKernelGGL((k_ensemble_step<S, R, G>), dim3(ntiles), dim3(kEnsembleBlock), 0,
+                       stream, static_cast<const S *>(src), static_cast<S *>(dst),
+                       static_cast<const ReplicaParams<R> *>(reps), tile_rep, step_ptr,
+                       partials);
+    return hipGetLastError();
+  };
+  auto by_general = [&](auto stt, auto rt) {
+    return general ? go(stt, rt, std::true_type{}) : go(stt, rt, std::false_type{});
+  };
+  switch (storage) {
+    case kF64: return by_general(Tag<double>{}, Tag<double>{});
+    case kF32: return by_general(Tag<float>{}, Tag<float>{});
+    case kF16: return by_general(Tag<__half>{}, Tag<float>{});
+    case kBF16: return by_general(Tag<__hip_bfloat16>{}, Tag<float>{});
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ensemble_finalize(int storage, const void *reps, int nrep,
+                                    const double *partials, double *series,
+                                    int cap, int64_t *step_ptr, double *mass0,
+                                    bool stats, hipStream_t stream) {
+  if (!stats) {
+    hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr);
+    return hipGetLastError();
+  }
+  if (storage == kF64)
+    hipLaunchKernelGGL(k_ensemble_reduce<double>, dim3(nrep), dim3(256), 0, stream,
+                       static_cast<const ReplicaParams<double> *>(reps), partials,
+                       series, cap, step_ptr, mass0);
+  else
+    hipLaunchKernelGGL(k_ensemble_reduce<float>, dim3(nrep), dim3(256), 0, stream,
+                       static_cast<const ReplicaParams<float> *>(reps), partials,
+                       series, cap, step_ptr, mass0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr);
   return hipGetLastError();
 }
 

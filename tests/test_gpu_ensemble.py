@@ -1,0 +1,116 @@
+"""Batched ensembles on the GPU: every replica of one fused launch evolves as
+a standalone lattice with the same descriptor, and one replica is checked
+against the FP64 oracle.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_16486_amd import Ensemble, Lattice, _lib
+from paper_2602_16486_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REPLICAS = [
+    {"q": 9, "shape": (37, 23), "kT": 1e-4, "tau": 0.7, "seed": 11, "replica": 0},
+    {"q": 27, "shape": (13, 9, 7), "kT": 3e-4, "tau": 0.55, "seed": 12, "replica": 1},
+    {"q": 9, "shape": (300, 5), "kT": 1e-5, "tau": 1.9, "seed": 13, "replica": 2, "rho0": 1.3},
+    {"q": 27, "shape": (20, 18, 16), "kT": 1e-3, "tau": 0.9, "seed": 14, "replica": 3},
+    {"q": 9, "shape": (64, 64), "kT": 0.0, "tau": 0.8, "seed": 15, "replica": 4},
+]
+
+
+def _state(r, seed):
+    q, shape = r["q"], r["shape"]
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, seed, rho0=r.get("rho0", 1.0), umax=0.04, dims=2 if q == 9 else 3)
+    return O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, seed + 1, 5e-4)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu_present():
+    assert _lib.device_count() > 0, "no HIP device visible: the gpu tests need an MI355X"
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_replicas_match_standalone_lattices(storage):
+    steps = 40  # one captured 32-step graph + 8 direct steps
+    states = [_state(r, 100 + k) for k, r in enumerate(REPLICAS)]
+    with Ensemble(REPLICAS, storage=storage) as ens:
+        info = ens.info
+        assert info["replicas"] == len(REPLICAS)
+        assert info["sites"] == sum(W.n_sites(r["shape"]) for r in REPLICAS)
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(steps)
+        assert ens.step_index == steps
+        got = [ens.get_populations(k) for k in range(len(REPLICAS))]
+        st = [ens.stats(k) for k in range(len(REPLICAS))]
+    for k, r in enumerate(REPLICAS):
+        kw = {key: r[key] for key in ("kT", "tau", "seed", "replica") if key in r}
+        with Lattice(r["q"], r["shape"], storage=storage, rho0=r.get("rho0", 1.0), **kw) as lat:
+            lat.set_populations(states[k])
+            lat.step(steps)
+            ref = lat.get_populations()
+            ref_st = lat.stats()
+        assert np.array_equal(got[k], ref), f"replica {k}"
+        assert st[k].shape == ref_st.shape
+        assert np.array_equal(st[k][:, 0], ref_st[:, 0])
+        # FP64 sums of identical per-site values in a different grouping
+        assert np.allclose(st[k], ref_st, rtol=1e-12, atol=1e-18), f"replica {k} statistics"
+
+
+def test_replica_matches_oracle():
+    r = REPLICAS[3]
+    f0 = _state(r, 7)
+    with Ensemble(REPLICAS, storage="f64") as ens:
+        ens.set_populations(3, f0)
+        ens.step(6)
+        got = ens.get_populations(3)
+    f = f0.copy()
+    O.run(27, r["shape"], f, r["kT"], O.paper_lambda(27, 1 / r["tau"]), r["seed"], r["replica"], 0, 6)
+    _, w = O.lattice(27)
+    assert np.abs(got - f).max() / np.abs(f - w[:, None]).max() < 1e-12
+
+
+def test_graph_replay_equals_direct_launches():
+    states = [_state(r, 200 + k) for k, r in enumerate(REPLICAS)]
+    out = []
+    for flags in (0, _lib.FLAG_NO_GRAPH):
+        with Ensemble(REPLICAS, storage="f32", flags=flags) as ens:
+            for k, f in enumerate(states):
+                ens.set_populations(k, f)
+            ens.step(70)
+            out.append([ens.get_populations(k) for k in range(len(REPLICAS))] +
+                       [ens.stats(k) for k in range(len(REPLICAS))])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_general_rates_replica_and_rest_replicas():
+    """A replica with a non-paper rate vector switches the ensemble to the
+    general kernel; the other replicas are unaffected (the general kernel with
+    the paper's rates gives the same result up to rounding)."""
+    reps = [dict(REPLICAS[1]), dict(REPLICAS[0])]
+    reps[0]["lam"] = np.linspace(0.5, 1.9, 27)
+    states = [_state(r, 300 + k) for k, r in enumerate(reps)]
+    with Ensemble(reps, storage="f64") as ens:
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(5)
+        got = [ens.get_populations(k) for k in range(2)]
+    _, w27 = O.lattice(27)
+    f = states[0].copy()
+    O.run(27, reps[0]["shape"], f, reps[0]["kT"], reps[0]["lam"], reps[0]["seed"], reps[0]["replica"], 0, 5)
+    assert np.abs(got[0] - f).max() / np.abs(f - w27[:, None]).max() < 1e-12
+    _, w9 = O.lattice(9)
+    g = states[1].copy()
+    O.run(9, reps[1]["shape"], g, reps[1]["kT"], O.paper_lambda(9, 1 / reps[1]["tau"]), reps[1]["seed"],
+          reps[1]["replica"], 0, 5)
+    assert np.abs(got[1] - g).max() / np.abs(g - w9[:, None]).max() < 1e-12
+
+
+def test_invalid_ensembles_are_rejected():
+    with pytest.raises(_lib.CmfError):
+        Ensemble([])
+    with pytest.raises(_lib.CmfError):
+        Ensemble([{"q": 9, "shape": (8, 8, 2)}])
