@@ -222,6 +222,30 @@ int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step,
 int cmf_philox_words(const uint32_t *ctr, int64_t n, uint32_t key0,
                      uint32_t key1, uint32_t *out);
 
+/* ---- static structure factor (amortized diagnostic) ----------------------
+ * S_a(k) = < |sum_x a(x) exp(-i k.x)|^2 > / N over sampled states, for
+ * a = drho (= rho - rho0), u_x, u_y, u_z of the pre-collision state; for the
+ * equilibrium of the method S_rho = rho0 kT / c_s^2 and S_u = kT / rho0 at
+ * every k != 0 (linearised equipartition).  Each sample computes the four
+ * FP32 fields on the device, transforms them with hipFFT (real-to-complex)
+ * and adds |F(k)|^2 / N to FP64 accumulators; shell averages over
+ * |k| = 2 pi sqrt((m_x/n_x)^2 + ...) are reduced in a fixed order. */
+
+/* Allocate (first call) and zero the accumulators, with `nbins` shells of
+ * equal width on [0, pi sqrt(d)] (1 <= nbins <= 1024).  Synchronous. */
+int cmf_sk_reset(cmf_lattice *lat, int32_t nbins);
+
+/* Add one sample: the current pre-collision state.  Asynchronous on the
+ * lattice's stream (call between steps, not inside captured graphs). */
+int cmf_sk_accumulate(cmf_lattice *lat);
+
+/* Shell averages of the samples so far: out[6 b + c] for shell b with
+ * c = 0 mean |k|, 1 number of modes (k = 0 excluded), 2 S_rho, 3 S_ux,
+ * 4 S_uy, 5 S_uz (averaged over samples and over the shell's modes; empty
+ * shells have 0 modes and zeros).  *nsamples receives the sample count.
+ * Synchronous. */
+int cmf_sk_shells(cmf_lattice *lat, double *out, int64_t *nsamples);
+
 /* ---- batched ensembles ------------------------------------------------
  * Many independent replicas (D2Q9 and D3Q27 mixed; uneven boxes; each with
  * its own tau / rates, kT, rho0, seed and replica number) advanced together

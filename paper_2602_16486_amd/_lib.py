@@ -122,6 +122,11 @@ def load():
     lib.cmf_ensemble_synchronize.argtypes = [vp]
     lib.cmf_ensemble_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_ensemble_stats.argtypes = [vp, i32, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_sk_reset.argtypes = [vp, i32]
+    lib.cmf_sk_accumulate.argtypes = [vp]
+    lib.cmf_sk_shells.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+    for name in ("cmf_sk_reset", "cmf_sk_accumulate", "cmf_sk_shells"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("cmf_ensemble_create", "cmf_ensemble_destroy", "cmf_ensemble_info",
                  "cmf_ensemble_init_equilibrium", "cmf_ensemble_set_populations",
                  "cmf_ensemble_get_populations", "cmf_ensemble_step", "cmf_ensemble_profile_steps",

@@ -39,10 +39,16 @@ def compile_flags():
     ]
 
 
+def link_flags():
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return [f"-L{rocm}/lib", "-lhipfft", f"-Wl,-rpath,{rocm}/lib"]
+
+
 def build(verbose=False):
     out = library_path()
     tmp = out + ".tmp"
-    cmd = [hipcc()] + compile_flags() + [os.path.join(HERE, s) for s in SOURCES] + ["-o", tmp]
+    cmd = ([hipcc()] + compile_flags() + [os.path.join(HERE, s) for s in SOURCES] + link_flags()
+           + ["-o", tmp])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -10,6 +10,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <hipfft/hipfft.h>
+
 #include <map>
 #include <mutex>
 #include <string>
@@ -171,6 +173,16 @@ struct cmf_lattice {
   StepParams<double> pd;
   ConvParams cp;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // structure factor
+  int sk_nbins = 0;
+  int64_t sk_M = 0, sk_samples = 0;
+  float *sk_fields = nullptr;
+  void *sk_F = nullptr;
+  double *sk_acc = nullptr, *sk_out = nullptr;
+  int32_t *sk_perm = nullptr;
+  int64_t *sk_off = nullptr;
+  hipfftHandle sk_plan = 0;
+  bool sk_has_plan = false;
 };
 
 namespace {
@@ -355,6 +367,10 @@ void release(cmf_lattice *L) {
   if (L->level2) (void)hipFree(L->level2);
   if (L->series) (void)hipFree(L->series);
   if (L->step_dev) (void)hipFree(L->step_dev);
+  if (L->sk_has_plan) (void)hipfftDestroy(L->sk_plan);
+  for (void *p : {(void *)L->sk_fields, L->sk_F, (void *)L->sk_acc, (void *)L->sk_out,
+                  (void *)L->sk_perm, (void *)L->sk_off})
+    if (p) (void)hipFree(p);
   if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
   delete L;
 }
@@ -638,6 +654,90 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
   for (auto &x : ev) (void)hipEventDestroy(x);
   *kernel_ms = total;
   return rc;
+}
+
+int cmf_sk_reset(cmf_lattice *L, int32_t nbins) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (nbins < 1 || nbins > 1024) return fail(CMF_EINVAL, "nbins must be in [1, 1024], got %d", nbins);
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  const int nx = L->desc.nx, ny = L->desc.ny, nz = L->desc.nz;
+  const int64_t M = (int64_t)(nx / 2 + 1) * ny * nz;
+  if (!L->sk_fields) {
+    if (hipMalloc((void **)&L->sk_fields, sizeof(float) * 4 * L->N) != hipSuccess ||
+        hipMalloc(&L->sk_F, sizeof(float) * 2 * 4 * M) != hipSuccess ||
+        hipMalloc((void **)&L->sk_acc, sizeof(double) * 4 * M) != hipSuccess ||
+        hipMalloc((void **)&L->sk_perm, sizeof(int32_t) * M) != hipSuccess)
+      return fail(CMF_ENOMEM, "structure-factor allocation failed");
+    hipfftResult fr = nz > 1 ? hipfftPlan3d(&L->sk_plan, nz, ny, nx, HIPFFT_R2C)
+                             : hipfftPlan2d(&L->sk_plan, ny, nx, HIPFFT_R2C);
+    if (fr != HIPFFT_SUCCESS) return fail(CMF_EHIP, "hipfft plan failed (%d)", (int)fr);
+    L->sk_has_plan = true;
+    if (hipfftSetStream(L->sk_plan, L->stream) != HIPFFT_SUCCESS)
+      return fail(CMF_EHIP, "hipfftSetStream failed");
+    L->sk_M = M;
+  }
+  if (L->sk_nbins != nbins) {
+    // shell of every mode on the device, counting sort by shell on the host
+    std::vector<int32_t> bin(M), perm(M);
+    std::vector<int64_t> off(nbins + 1, 0);
+    HIP_TRY(launch_sk_shell_index(nx, ny, nz, nbins, M, L->sk_perm, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    HIP_TRY(hipMemcpy(bin.data(), L->sk_perm, sizeof(int32_t) * M, hipMemcpyDeviceToHost));
+    for (int64_t m = 0; m < M; ++m)
+      if (bin[m] >= 0) ++off[bin[m] + 1];
+    for (int b = 0; b < nbins; ++b) off[b + 1] += off[b];
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t m = 0; m < M; ++m)
+      if (bin[m] >= 0) perm[pos[bin[m]]++] = (int32_t)m;
+    if (L->sk_off) (void)hipFree(L->sk_off);
+    if (L->sk_out) (void)hipFree(L->sk_out);
+    L->sk_off = nullptr;
+    L->sk_out = nullptr;
+    if (hipMalloc((void **)&L->sk_off, sizeof(int64_t) * (nbins + 1)) != hipSuccess ||
+        hipMalloc((void **)&L->sk_out, sizeof(double) * 6 * nbins) != hipSuccess)
+      return fail(CMF_ENOMEM, "structure-factor allocation failed");
+    HIP_TRY(hipMemcpy(L->sk_perm, perm.data(), sizeof(int32_t) * off[nbins], hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(L->sk_off, off.data(), sizeof(int64_t) * (nbins + 1), hipMemcpyHostToDevice));
+    L->sk_nbins = nbins;
+  }
+  HIP_TRY(hipMemsetAsync(L->sk_acc, 0, sizeof(double) * 4 * M, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  L->sk_samples = 0;
+  return CMF_OK;
+}
+
+int cmf_sk_accumulate(cmf_lattice *L) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (!L->sk_nbins) return fail(CMF_EINVAL, "call cmf_sk_reset first");
+  HIP_TRY(launch_macro_dev(L->q, L->storage, L->cp, L->buf[L->parity], L->sk_fields, L->stream));
+  for (int f = 0; f < 4; ++f) {
+    hipfftResult fr = hipfftExecR2C(L->sk_plan, (hipfftReal *)(L->sk_fields + f * L->N),
+                                    (hipfftComplex *)L->sk_F + f * L->sk_M);
+    if (fr != HIPFFT_SUCCESS) return fail(CMF_EHIP, "hipfftExecR2C failed (%d)", (int)fr);
+  }
+  HIP_TRY(launch_sk_accumulate(L->sk_F, L->sk_M, 1.0 / (double)L->N, L->sk_acc, L->stream));
+  ++L->sk_samples;
+  return CMF_OK;
+}
+
+int cmf_sk_shells(cmf_lattice *L, double *out, int64_t *nsamples) {
+  if (!L || !out) return fail(CMF_EINVAL, "NULL argument");
+  if (!L->sk_nbins) return fail(CMF_EINVAL, "call cmf_sk_reset first");
+  const int nb = L->sk_nbins;
+  HIP_TRY(launch_sk_segments(L->sk_acc, L->sk_M, L->desc.nx, L->desc.ny, L->desc.nz, nb,
+                             L->sk_perm, L->sk_off, L->sk_out, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  std::vector<double> raw(6 * nb);
+  HIP_TRY(hipMemcpy(raw.data(), L->sk_out, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost));
+  const double ns = L->sk_samples > 0 ? (double)L->sk_samples : 1.0;
+  for (int b = 0; b < nb; ++b) {
+    const double w = raw[6 * b + 1];
+    out[6 * b + 0] = w > 0 ? raw[6 * b] / w : 0.0;
+    out[6 * b + 1] = w;
+    for (int c = 2; c < 6; ++c) out[6 * b + c] = w > 0 ? raw[6 * b + c] / w / ns : 0.0;
+  }
+  if (nsamples) *nsamples = L->sk_samples;
+  return CMF_OK;
 }
 
 int cmf_get_launch(cmf_lattice *L, cmf_launch *out) {

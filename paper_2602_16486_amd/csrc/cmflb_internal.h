@@ -87,7 +87,18 @@ hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
                               hipStream_t stream);
 
-// ensemble (cmflb_ensemble.hip)
+// structure factor
+hipError_t launch_macro_dev(int q, int storage, const ConvParams &cp,
+                            const void *buf, float *out, hipStream_t stream);
+hipError_t launch_sk_accumulate(const void *F, int64_t M, double inv_n,
+                                double *acc, hipStream_t stream);
+hipError_t launch_sk_shell_index(int nx, int ny, int nz, int nbins, int64_t M,
+                                 int32_t *bin, hipStream_t stream);
+hipError_t launch_sk_segments(const double *acc, int64_t M, int nx, int ny, int nz,
+                              int nbins, const int32_t *perm, const int64_t *off,
+                              double *out, hipStream_t stream);
+
+// ensemble
 constexpr int kEnsembleBlock = 256;
 hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
                                 const int32_t *tile_rep, int ntiles,

@@ -569,6 +569,115 @@ __global__ void k_zero_i64(int64_t *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// structure factor (amortized diagnostic): fields, |FFT|^2 accumulation and
+// deterministic shell binning
+// ---------------------------------------------------------------------------
+// drho = rho - rho0, u_x, u_y, u_z of the pre-collision state as 4 FP32
+// planes of N values (FP64 arithmetic, rounded once).
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_macro_dev(const ConvParams cp,
+                                                   const S *__restrict__ buf,
+                                                   float *__restrict__ out) {
+  using ST = Store<S, double>;
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const double d = ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+                              cp.scale[i]);
+    drho += d;
+    j[0] += L::cx[i] * d;
+    j[1] += L::cy[i] * d;
+    j[2] += L::cz[i] * d;
+  }
+  const double rho = cp.rho0 + drho;
+  out[s] = (float)drho;
+  out[N + s] = (float)(j[0] / rho);
+  out[2 * N + s] = (float)(j[1] / rho);
+  out[3 * N + s] = (float)(j[2] / rho);
+}
+
+// acc[f][m] += |F_f(m)|^2 / N for the 4 transformed fields (M modes each)
+__global__ __launch_bounds__(256) void k_sk_accumulate(
+    const float2 *__restrict__ F, int64_t M, double inv_n,
+    double *__restrict__ acc) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= 4 * M) return;
+  const float2 c = F[m];
+  acc[m] += ((double)c.x * c.x + (double)c.y * c.y) * inv_n;
+}
+
+// shell of half-spectrum mode m (nxh = nx/2 + 1 modes along x), with the
+// Hermitian weight of the modes the real transform does not store
+struct ShellGeom {
+  int nx, ny, nz, nxh, nbins;
+  double kmax;
+};
+
+__device__ __forceinline__ int shell_of(const ShellGeom &g, int64_t m,
+                                        double *weight, double *kmag) {
+  const int kx = (int)(m % g.nxh);
+  const int64_t r = m / g.nxh;
+  const int ky0 = (int)(r % g.ny), kz0 = (int)(r / g.ny);
+  const int ky = ky0 <= g.ny / 2 ? ky0 : ky0 - g.ny;
+  const int kz = kz0 <= g.nz / 2 ? kz0 : kz0 - g.nz;
+  const double two_pi = 6.283185307179586;
+  const double ax = two_pi * kx / g.nx, ay = two_pi * ky / g.ny,
+               az = two_pi * kz / g.nz;
+  const double k = sqrt(ax * ax + ay * ay + az * az);
+  *kmag = k;
+  const bool self = kx == 0 || (g.nx % 2 == 0 && kx == g.nx / 2);
+  *weight = self ? 1.0 : 2.0;
+  if (kx == 0 && ky == 0 && kz == 0) return -1;  // k = 0 excluded
+  int b = (int)(k / g.kmax * g.nbins);
+  return b < g.nbins ? b : g.nbins - 1;
+}
+
+// shell index of every half-spectrum mode (-1 for k = 0)
+__global__ __launch_bounds__(256) void k_sk_shell_index(const ShellGeom g, int64_t M,
+                                                        int32_t *__restrict__ bin) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double w, k;
+  bin[m] = shell_of(g, m, &w, &k);
+}
+
+// one workgroup per shell sums its modes (listed contiguously in `perm`,
+// shell b in [off[b], off[b + 1])) in a fixed order:
+// out[b] = (sum w k, sum w, sum w S_rho, sum w S_ux, sum w S_uy, sum w S_uz)
+constexpr int kSkCols = 6;
+__global__ __launch_bounds__(256) void k_sk_segments(const double *__restrict__ acc,
+                                                     int64_t M, const ShellGeom g,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int64_t *__restrict__ off,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[256][kSkCols];
+  const int b = blockIdx.x;
+  double s[kSkCols] = {0, 0, 0, 0, 0, 0};
+  for (int64_t j = off[b] + threadIdx.x; j < off[b + 1]; j += blockDim.x) {
+    const int64_t m = perm[j];
+    double w, k;
+    shell_of(g, m, &w, &k);
+    s[0] += w * k;
+    s[1] += w;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) s[2 + f] += w * acc[f * M + m];
+  }
+#pragma unroll
+  for (int c = 0; c < kSkCols; ++c) sh[threadIdx.x][c] = s[c];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int c = 0; c < kSkCols; ++c) sh[threadIdx.x][c] += sh[threadIdx.x + h][c];
+    __syncthreads();
+  }
+  if (threadIdx.x < kSkCols) out[(int64_t)b * kSkCols + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // batched ensemble: one launch per step over the tiles of every replica
 // ---------------------------------------------------------------------------
 // A tile is kEnsembleBlock consecutive sites (x fastest) of one replica, so
@@ -904,6 +1013,53 @@ hipError_t launch_ensemble_finalize(int storage, const void *reps, int nrep,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_macro_dev(int q, int storage, const ConvParams &cp,
+                            const void *buf, float *out, hipStream_t stream) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_macro_dev<L, S>), dim3(blocks_for(N, 256)), dim3(256), 0,
+                       stream, cp, static_cast<const S *>(buf), out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_sk_accumulate(const void *F, int64_t M, double inv_n,
+                                double *acc, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sk_accumulate, dim3(blocks_for(4 * M, 256)), dim3(256), 0,
+                     stream, static_cast<const float2 *>(F), M, inv_n, acc);
+  return hipGetLastError();
+}
+
+ShellGeom shell_geom(int nx, int ny, int nz, int nbins) {
+  ShellGeom g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.nxh = nx / 2 + 1;
+  g.nbins = nbins;
+  const double pi = 3.141592653589793;
+  g.kmax = pi * sqrt((nx > 1 ? 1.0 : 0.0) + (ny > 1 ? 1.0 : 0.0) + (nz > 1 ? 1.0 : 0.0)) *
+           (1.0 + 1e-12);
+  return g;
+}
+
+hipError_t launch_sk_shell_index(int nx, int ny, int nz, int nbins, int64_t M,
+                                 int32_t *bin, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sk_shell_index, dim3(blocks_for(M, 256)), dim3(256), 0, stream,
+                     shell_geom(nx, ny, nz, nbins), M, bin);
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_segments(const double *acc, int64_t M, int nx, int ny, int nz,
+                              int nbins, const int32_t *perm, const int64_t *off,
+                              double *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sk_segments, dim3(nbins), dim3(256), 0, stream, acc, M,
+                     shell_geom(nx, ny, nz, nbins), perm, off, out);
   return hipGetLastError();
 }
 

@@ -100,6 +100,22 @@ class Lattice:
         _lib.check(self._lib.cmf_profile_steps(self._h, int(n), ctypes.byref(ms)))
         return ms.value
 
+    # -- structure factor --------------------------------------------------
+    def sk_reset(self, nbins=64):
+        self._sk_nbins = int(nbins)
+        _lib.check(self._lib.cmf_sk_reset(self._h, int(nbins)))
+
+    def sk_accumulate(self):
+        _lib.check(self._lib.cmf_sk_accumulate(self._h))
+
+    def sk_shells(self):
+        """(nbins, 6) array: mean |k|, modes, S_rho, S_ux, S_uy, S_uz; and
+        the number of samples."""
+        out = np.zeros((self._sk_nbins, 6))
+        ns = ctypes.c_int64()
+        _lib.check(self._lib.cmf_sk_shells(self._h, _lib._d(out), ctypes.byref(ns)))
+        return out, ns.value
+
     # -- launch shape -------------------------------------------------------
     @property
     def launch(self):
