@@ -1,0 +1,226 @@
+"""Statistical validation runs on the GPU: the paper's Tests 3-7 (Sec. 3)
+and the larger configurations of the project's benchmark plan, all on
+synthetic rest-state inputs.  Each run prints one JSON line.
+
+    python -m paper_2602_16486_amd.experiments NAME [--scale S]
+
+NAME: test3 test4 test5 test6 test7 config2 config3 config4 config5, or all.
+--scale multiplies the number of steps (default 1; the paper's durations
+are used at scale 1 where they are stated).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import stats as S
+from . import workloads as W
+from .ensemble import Ensemble
+from .lattice import Lattice
+
+CS2 = 1.0 / 3.0
+
+
+def _emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def run(q, shape, storage="f32", steps=1000, tau=0.8, kT=1e-4, rho0=1.0, seed=1, lam=None,
+        window=0.5, sk_every=0, nbins=32, chunk=1 << 16):
+    """Step a rest-state lattice, collecting the per-step <u_a^2> series and
+    optionally the structure factor over the window.  Returns diagnostics."""
+    dims = 2 if q == 9 else 3
+    n = W.n_sites(shape)
+    start = int(steps * (1 - window))
+    u2 = np.zeros((steps, 3))
+    got = 0
+    first = last = None
+    t0 = time.perf_counter()
+    with Lattice(q, shape, storage=storage, rho0=rho0, tau=tau, kT=kT, lam=lam, seed=seed,
+                 series_capacity=chunk) as lat:
+        if sk_every:
+            lat.sk_reset(nbins)
+        done = unread = 0
+        while done < steps:
+            k = min(chunk - unread, steps - done)
+            if sk_every and done >= start:
+                if (done - start) % sk_every == 0:
+                    lat.sk_accumulate()  # the state of step `done`
+                k = min(k, sk_every - (done - start) % sk_every)
+            elif sk_every:
+                k = min(k, start - done)
+            lat.step(k)
+            done += k
+            unread += k
+            if unread >= chunk or done == steps:
+                st = lat.stats(cap=chunk, raise_nonfinite=False)
+                if st[:, 11].any():
+                    return {"nonfinite": True, "step": int(st[st[:, 11] > 0][0, 0])}
+                if first is None:
+                    first = st[0].copy()
+                last = st[-1].copy()
+                u2[got:got + len(st)] = st[:, 8:11]
+                got += len(st)
+                unread = 0
+        sk = lat.sk_shells()[0] if sk_every else None
+    series = np.zeros((steps, 12))
+    series[:, 8:11] = u2
+    out = S.equipartition(series, n, kT, rho0, dims, start=start)
+    out["mass_drift"] = float(last[1] - first[1])
+    out["momentum_drift"] = float(np.abs(last[2:5] - first[2:5]).max())
+    out["seconds"] = time.perf_counter() - t0
+    if sk is not None:
+        w = sk[:, 1]
+        su = sk[:, 3:3 + dims].mean(axis=1) / (kT / rho0)
+        sr = sk[:, 2] / (rho0 * kT / CS2)
+        big = w >= 50
+        out["S_u_mean"] = float(np.average(su, weights=w))
+        out["S_rho_mean"] = float(np.average(sr, weights=w))
+        out["S_u_max_dev"] = float(np.abs(su[big] - 1).max())
+        out["S_rho_max_dev"] = float(np.abs(sr[big] - 1).max())
+        out["S_u_shells"] = su.round(5).tolist()
+    return out
+
+
+def test3(scale):
+    """Test 3: D2Q9 200x200, rho0 = 1, tau = 0.8, kT = 1/3000, T_max = 100 t0
+    with t0 = N_y / u0 = 200 / 0.01 (2e6 steps); Table 2 quantities."""
+    steps = int(2_000_000 * scale)
+    r = run(9, (200, 200), steps=steps, tau=0.8, kT=1 / 3000, window=0.99)
+    _emit({"experiment": "test3", "steps": steps, **r,
+           "paper_table2": {"ux2": [8.76e-7, 2.4e-6], "uy2": [6.31e-7, 2.5e-6], "e": [7.54e-7, 1.8e-6]}})
+
+
+def test4(scale):
+    """Test 4: <u_a^2> linear in kT (kT in {1/6000, 1/3000, 1/1500, 1/750})."""
+    for kT in (1 / 6000, 1 / 3000, 1 / 1500, 1 / 750):
+        r = run(9, (200, 200), steps=int(200_000 * scale), tau=0.8, kT=kT)
+        _emit({"experiment": "test4", "kT": kT, **r})
+
+
+def test5(scale):
+    """Test 5: <u_a^2> proportional to 1/rho0 (rho0 in {0.5, 1, 2, 4})."""
+    for rho0 in (0.5, 1.0, 2.0, 4.0):
+        r = run(9, (200, 200), steps=int(200_000 * scale), tau=0.8, kT=1 / 3000, rho0=rho0)
+        _emit({"experiment": "test5", "rho0": rho0, **r})
+
+
+def test6(scale):
+    """Test 6: tau sweep, the paper's rates against a single rate for every
+    mode (Lambda = omega I), psi of each."""
+    taus = (0.5, 0.5001, 0.5005, 0.501, 0.505, 0.51, 0.55, 0.7, 1.0, 1.5, 2.0, 5.0, 10.0, 50.0, 100.0)
+    for tau in taus:
+        for kind in ("cm", "single_rate"):
+            lam = None if kind == "cm" else np.full(9, 1 / tau)
+            r = run(9, (200, 200), steps=int(100_000 * scale), tau=tau, kT=1 / 3000, lam=lam)
+            _emit({"experiment": "test6", "tau": tau, "rates": kind, **r})
+
+
+def test7(scale):
+    """Test 7: D3Q27 on anisotropic boxes C1-C4, kT = 1/3000, tau = 0.8,
+    T_max = 100 t0 with t0 = N_y / 0.01; Table 3 quantities."""
+    boxes = {"C1": (50, 50, 50), "C2": (25, 50, 100), "C3": (60, 15, 30), "C4": (20, 80, 40)}
+    paper = {"C1": [1.42e-6, 1.62e-6, 7.0e-8], "C2": [1.43e-6, 1.62e-6, 9.0e-8],
+             "C3": [1.25e-6, 2.26e-6, 2.0e-8], "C4": [8.30e-7, 1.25e-6, 1.8e-7]}
+    for name, shape in boxes.items():
+        steps = int(100 * shape[1] / 0.01 * scale)
+        r = run(27, shape, steps=steps, tau=0.8, kT=1 / 3000, window=0.99)
+        _emit({"experiment": "test7", "box": name, "shape": shape, "steps": steps, **r,
+               "paper_table3": paper[name]})
+
+
+def config2(scale):
+    """D2Q9 1024^2, FP32 and FP64 storage, kT x tau grid, 20000 steps,
+    averages and S(k) (every 100 steps) over steps 10000-20000."""
+    for storage in ("f32", "f64"):
+        for kT in (1e-6, 1e-5, 1e-4):
+            for tau in (0.501, 0.6, 1.0, 2.0):
+                r = run(9, (1024, 1024), storage=storage, steps=int(20_000 * scale), tau=tau, kT=kT,
+                        sk_every=100, nbins=48)
+                r.pop("S_u_shells", None)
+                _emit({"experiment": "config2", "storage": storage, "kT": kT, "tau": tau, **r})
+
+
+def config3(scale):
+    """D3Q27 128^3, rho0 in {0.5, 1, 2}, tau = 0.55, kT = 1e-4, 10000 steps,
+    averages over steps 2000-10000: isotropy and 1/rho0 scaling."""
+    for rho0 in (0.5, 1.0, 2.0):
+        r = run(27, (128, 128, 128), steps=int(10_000 * scale), tau=0.55, kT=1e-4, rho0=rho0, window=0.8)
+        _emit({"experiment": "config3", "rho0": rho0, **r})
+
+
+def config4(scale):
+    """D3Q27 256^3, FP32 / FP16 / BF16 storage (same noise), tau in
+    {0.51, 0.8}, kT in {1e-5, 1e-4}: <u^2> and S(k) of the 16-bit runs
+    against the FP32 run."""
+    steps = int(2000 * scale)
+    for tau in (0.51, 0.8):
+        for kT in (1e-5, 1e-4):
+            ref_u2 = ref_shells = None
+            for storage in ("f32", "f16", "bf16"):
+                r = run(27, (256, 256, 256), storage=storage, steps=steps, tau=tau, kT=kT,
+                        sk_every=50, nbins=48)
+                rec = {"experiment": "config4", "storage": storage, "tau": tau, "kT": kT, "steps": steps}
+                shells = np.array(r.pop("S_u_shells"))
+                u2 = float(np.mean(r["u2_over_target"]))
+                if ref_u2 is None:
+                    ref_u2, ref_shells = u2, shells
+                else:
+                    rec["u2_rel_diff_vs_f32"] = abs(u2 / ref_u2 - 1)
+                    rec["S_u_max_shell_rel_diff_vs_f32"] = float(np.max(np.abs(shells / ref_shells - 1)))
+                _emit({**rec, **r})
+
+
+def config5(scale):
+    """The batched ensemble (256 D2Q9 + 64 D3Q27 replicas), 5000 steps:
+    per-replica equipartition over steps 2500-5000."""
+    manifest = W.ensemble_manifest()
+    steps = int(5000 * scale)
+    t0 = time.perf_counter()
+    with Ensemble(manifest, storage="f32", series_capacity=steps) as ens:
+        ens.step(steps)
+        ens.synchronize()
+        secs = time.perf_counter() - t0
+        ratios, bands, inband = [], [], 0
+        for k, r in enumerate(manifest):
+            st = ens.stats(k, cap=steps, raise_nonfinite=False)
+            dims = 2 if r["q"] == 9 else 3
+            n = W.n_sites(r["shape"])
+            d = S.equipartition(st, n, r["kT"], r["rho0"], dims, start=steps // 2)
+            ratio = float(np.mean(d["u2_over_target"]))
+            # statistical band: 5 x white-noise RMS / sqrt(window / 50) plus
+            # the nonlinear shift (~9 kT/rho0) and the 2-D warm-up deficit
+            # 1 / (8 pi nu t) of slow replicas
+            nu = CS2 * (r["tau"] - 0.5)
+            band = (5 * d["rms_white"] / (r["kT"] / r["rho0"]) / math.sqrt(d["steps"] / 50)
+                    + 9 * r["kT"] / r["rho0"] + (1 / (8 * math.pi * nu * steps / 2) if dims == 2 else 0))
+            ratios.append(ratio)
+            bands.append(band)
+            inband += abs(ratio - 1) <= band
+    _emit({"experiment": "config5", "replicas": len(manifest), "steps": steps, "seconds": secs,
+           "u2_over_target_median": float(np.median(ratios)),
+           "u2_over_target_min_max": [float(min(ratios)), float(max(ratios))],
+           "replicas_within_band": int(inband)})
+
+
+EXPERIMENTS = {f.__name__: f for f in (test3, test4, test5, test6, test7, config2, config3, config4, config5)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="+")
+    ap.add_argument("--scale", type=float, default=1.0)
+    args = ap.parse_args(argv)
+    names = list(EXPERIMENTS) if args.names == ["all"] else args.names
+    for name in names:
+        print(f"# {name}", file=sys.stderr, flush=True)
+        EXPERIMENTS[name](args.scale)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,93 @@
+"""The benchmark configurations at sizes the oracle finishes in seconds:
+config 1 in full (D2Q9 64^2, 2000 steps) and a 48^3 subrun of config 4
+(FP32 / FP16 / BF16 storage against the FP64 oracle).  Needs an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import spectra
+from paper_2602_16486_amd import Lattice, _lib
+from paper_2602_16486_amd import stats as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu_present():
+    assert _lib.device_count() > 0, "no HIP device visible: the gpu tests need an MI355X"
+
+
+@pytest.fixture(scope="module")
+def config1_oracle():
+    q, shape, kT, steps = 9, (64, 64), 1e-4, 2000
+    f = O.init_equilibrium(q, 4096, rho0=1.0)
+    st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), 1, 0, 0, steps)
+    return f, st
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_config1_full_run(storage, config1_oracle):
+    """D2Q9 64x64, rho0 = 1, tau = 0.8, kT = 1e-4, Philox seed 1, 2000 steps
+    from rest: fields against the oracle, equipartition, conservation."""
+    q, shape, kT, steps = 9, (64, 64), 1e-4, 2000
+    f_ref, st_ref = config1_oracle
+    with Lattice(q, shape, storage=storage, tau=0.8, kT=kT, seed=1) as lat:
+        lat.step(steps)
+        got = lat.get_populations()
+        st = lat.stats()
+    _, w = O.lattice(q)
+    err = np.abs(got - f_ref).max() / np.abs(f_ref - w[:, None]).max()
+    tol = 1e-11 if storage == "f64" else 3e-6 * (1 + math.sqrt(steps))
+    print(f"config1 {storage}: rel err after {steps} steps {err:.3e} (tol {tol:.1e})")
+    assert err < tol
+    eq = S.equipartition(st, 4096, kT, 1.0, 2, start=200)
+    eq_ref = S.equipartition(st_ref, 4096, kT, 1.0, 2, start=200)
+    target = 1 - 1 / 4096
+    assert all(abs(r / target - 1) < 0.015 for r in eq["u2_over_target"])
+    assert np.allclose(eq["u2_over_target"], eq_ref["u2_over_target"], rtol=1e-9 if storage == "f64" else 1e-4)
+    c = S.conservation(st)
+    assert c["mass_drift"] < (1e-9 if storage == "f64" else 1e-4)
+    assert c["momentum_drift"] < (1e-10 if storage == "f64" else 1e-4)
+
+
+@pytest.fixture(scope="module")
+def config4_subrun_oracle():
+    q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
+    n = 48 ** 3
+    f = O.init_equilibrium(q, n, 1.0)
+    lam = O.paper_lambda(q, 1 / tau)
+    sa = spectra.ShellAverager(shape, 16)
+    rows = []
+    for k in range(steps // every):
+        rows.append(O.run(q, shape, f, kT, lam, 1, 0, k * every, every))
+        sa.add(spectra.fields(q, shape, f, 1.0))
+    return np.concatenate(rows), sa.shells()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_config4_subrun_against_oracle(storage, config4_subrun_oracle):
+    """48^3 subrun of the 256^3 storage comparison: <u^2> (averaged over the
+    run) within 1% of the FP64 oracle for every storage type, and the
+    structure factor shells within 2% (FP32 within 1e-4)."""
+    q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
+    st_ref, sk_ref = config4_subrun_oracle
+    with Lattice(q, shape, storage=storage, tau=tau, kT=kT, seed=1) as lat:
+        lat.sk_reset(16)
+        for _ in range(steps // every):
+            lat.step(every)
+            lat.sk_accumulate()
+        st = lat.stats()
+        sk, _ = lat.sk_shells()
+    n = 48 ** 3
+    u2 = st[:, 8:11].sum(axis=1) / n
+    u2_ref = st_ref[:, 8:11].sum(axis=1) / n
+    rel = abs(u2[20:].mean() / u2_ref[20:].mean() - 1)
+    per_step = np.abs(u2 / u2_ref - 1).max()
+    print(f"config4 subrun {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
+    assert rel < (1e-4 if storage == "f32" else 1e-2)
+    sel = sk_ref[:, 1] > 0
+    srel = np.abs(sk[sel, 2:5] / sk_ref[sel, 2:5] - 1).max()
+    print(f"config4 subrun {storage}: S(k) worst shell rel diff {srel:.2e}")
+    assert srel < (1e-4 if storage == "f32" else 2e-2)
