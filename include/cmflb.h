@@ -117,7 +117,7 @@ int cmf_device_count(void);
  * storage type plus statistics scratch.  The populations start at rest
  * (f = w rho0) at step 0.  `hip_stream` is a hipStream_t or NULL.
  * Errors: CMF_EINVAL (bad sizes, tau < 0.5, kT < 0, rho0 <= 0, rates out of
- * [0, 2], N >= 2^31), CMF_ENOMEM, CMF_EHIP. */
+ * [0, 2], N >= 2^31, nx >= 2^28), CMF_ENOMEM, CMF_EHIP. */
 int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
 
 /* Release all device memory of the lattice (synchronises its stream). */
@@ -259,9 +259,10 @@ typedef struct cmf_ensemble cmf_ensemble;
 
 /* Create an ensemble of n >= 1 replicas from n descriptors (validated as in
  * cmf_create; storage and flags must agree; series_capacity of descs[0]
- * applies to all).  All replicas start at rest at step 0.  Allocates two
- * population arenas holding every replica, the replica records, the tile
- * map and the statistics buffers.  Errors: CMF_EINVAL, CMF_ENOMEM,
+ * applies to all; each replica's q x N populations must take below 4 GiB
+ * in the storage type).  All replicas start at rest at step 0.  Allocates
+ * two population arenas holding every replica, the replica records, the
+ * tile map and the statistics buffers.  Errors: CMF_EINVAL, CMF_ENOMEM,
  * CMF_EHIP. */
 int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream,
                         cmf_ensemble **out);

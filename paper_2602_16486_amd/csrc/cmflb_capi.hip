@@ -101,6 +101,12 @@ int env_int(const char *name, int dflt) {
   return atoi(s);
 }
 
+// env_int clamped to [lo, hi]
+int env_int(const char *name, int dflt, int lo, int hi) {
+  const int v = env_int(name, dflt);
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
 }  // namespace
 
 namespace {
@@ -147,6 +153,7 @@ struct cmf_lattice {
   int q = 0;
   int storage = 0;
   bool general = false;
+  bool nt_stores = true;  // population rows are whole cache lines
   bool own_stream = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -305,7 +312,7 @@ const void *step_params(const cmf_lattice *L) {
 int enqueue_one_step(cmf_lattice *L) {
   const void *src = L->buf[L->parity];
   void *dst = L->buf[1 - L->parity];
-  HIP_TRY(launch_step(L->q, L->storage, L->general, step_params(L), src, dst,
+  HIP_TRY(launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst,
                       L->step_dev, L->partials, L->grid, L->block, L->stream));
   HIP_TRY(launch_finalize(L->partials, L->nparts, L->level2, L->series, L->cap,
                           L->step_dev, L->mass0,
@@ -383,6 +390,7 @@ int validate(const cmf_desc *d) {
   if (d->q == 9 && d->nz != 1) return fail(CMF_EINVAL, "D2Q9 needs nz = 1, got %d", d->nz);
   const int64_t N = (int64_t)d->nx * d->ny * d->nz;
   if (N >= (int64_t)1 << 31) return fail(CMF_EINVAL, "N = %lld sites exceeds 2^31 - 1", (long long)N);
+  if (d->nx >= (1 << 28)) return fail(CMF_EINVAL, "nx = %d is not below 2^28", d->nx);
   if (d->storage < kF64 || d->storage > kBF16) return fail(CMF_EINVAL, "unknown storage %d", d->storage);
   if (!(d->rho0 > 0.0) || !isfinite(d->rho0)) return fail(CMF_EINVAL, "rho0 must be > 0");
   if (!(d->tau >= 0.5) || !isfinite(d->tau)) return fail(CMF_EINVAL, "tau must be >= 0.5");
@@ -428,6 +436,7 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
   ModeConstants mc;
   mode_constants(desc, mc);
   L->general = mc.general;
+  L->nt_stores = ((int64_t)desc->nx * storage_bytes(desc->storage)) % kLineBytes == 0;
   double amp[27];
   float scale[27];
   for (int v = 0; v < q; ++v) {
@@ -633,7 +642,7 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
     void *dst = L->buf[1 - L->parity];
     hipError_t e = hipEventRecord(ev[2 * s], L->stream);
     if (e == hipSuccess)
-      e = launch_step(L->q, L->storage, L->general, step_params(L), src, dst, L->step_dev,
+      e = launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst, L->step_dev,
                       L->partials, L->grid, L->block, L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
     if (e == hipSuccess)
@@ -976,13 +985,14 @@ struct cmf_ensemble {
     cmf_desc desc;
     int64_t N = 0;
     int64_t offset = 0;  // elements
-    int tile0 = 0, ntiles = 0;
+    int tile0 = 0, ntiles = 0, spt = 1;
     ConvParams cp;
   };
   int n = 0;
   int storage = 1;
   uint32_t flags = 0;
   bool general = false;
+  bool nt_stores = true;  // every replica's population rows are whole cache lines
   bool own_stream = false;
   hipStream_t stream = nullptr;
   std::vector<Rep> reps;
@@ -1015,6 +1025,7 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
   p.nsites = (int32_t)rp.N;
   p.tile0 = rp.tile0;
   p.ntiles = rp.ntiles;
+  p.spt = rp.spt;
   p.noise = d.kT > 0.0 ? 1 : 0;
   p.offset = rp.offset;
   p.key0 = (uint32_t)d.seed;
@@ -1048,7 +1059,7 @@ void ens_release(cmf_ensemble *E) {
 }
 
 int ens_enqueue_step(cmf_ensemble *E) {
-  HIP_TRY(launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
+  HIP_TRY(launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
                                E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
                                E->partials, E->stream));
   HIP_TRY(launch_ensemble_finalize(E->storage, E->d_reps, E->n, E->partials, E->series, E->cap,
@@ -1101,6 +1112,12 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     if (rc != CMF_OK) return fail(rc, "replica %d: %s", r, g_last_error.c_str());
     if (descs[r].storage != descs[0].storage) return fail(CMF_EINVAL, "replica %d: storage differs from replica 0", r);
     if (descs[r].flags != descs[0].flags) return fail(CMF_EINVAL, "replica %d: flags differ from replica 0", r);
+    // ensemble tiles address a replica's buffer with 32-bit byte offsets
+    const int64_t bytes = (int64_t)descs[r].q * descs[r].nx * descs[r].ny * descs[r].nz *
+                          storage_bytes(descs[r].storage);
+    if (bytes >= ((int64_t)1 << 32))
+      return fail(CMF_EINVAL, "replica %d: %lld population bytes; an ensemble member holds below 4 GiB",
+                  r, (long long)bytes);
   }
   cmf_ensemble *E = new cmf_ensemble();
   E->n = n;
@@ -1120,6 +1137,7 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     offset += ((int64_t)descs[r].q * rp.N + 63) / 64 * 64;
     mode_constants(&descs[r], mcs[r]);
     if (mcs[r].general) E->general = true;
+    if (((int64_t)descs[r].nx * storage_bytes(descs[r].storage)) % kLineBytes != 0) E->nt_stores = false;
     rp.cp.nx = descs[r].nx;
     rp.cp.ny = descs[r].ny;
     rp.cp.nz = descs[r].nz;
@@ -1131,6 +1149,10 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     }
     E->total_sites += rp.N;
   }
+  // sites per thread (CMF_ENSEMBLE_SPT9 / CMF_ENSEMBLE_SPT27 override the
+  // defaults, 1..16)
+  const int spt9 = env_int("CMF_ENSEMBLE_SPT9", kEnsembleSpt9, 1, 16);
+  const int spt27 = env_int("CMF_ENSEMBLE_SPT27", kEnsembleSpt27, 1, 16);
   // tiles: D3Q27 replicas first, then D2Q9, each in creation order
   std::vector<int32_t> tile_rep;
   for (int pass = 0; pass < 2; ++pass)
@@ -1138,7 +1160,9 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
       if ((pass == 0) != (descs[r].q == 27)) continue;
       cmf_ensemble::Rep &rp = E->reps[r];
       rp.tile0 = (int)tile_rep.size();
-      rp.ntiles = (int)((rp.N + kEnsembleBlock - 1) / kEnsembleBlock);
+      rp.spt = descs[r].q == 27 ? spt27 : spt9;
+      const int64_t tsites = (int64_t)rp.spt * kEnsembleBlock;
+      rp.ntiles = (int)((rp.N + tsites - 1) / tsites);
       if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31)) {
         ens_release(E);
         return fail(CMF_EINVAL, "ensemble has too many tiles");
@@ -1298,7 +1322,7 @@ int cmf_ensemble_profile_steps(cmf_ensemble *E, int64_t nsteps, double *kernel_m
   for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
     e = hipEventRecord(ev[2 * s], E->stream);
     if (e == hipSuccess)
-      e = launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
+      e = launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
                                E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
                                E->partials, E->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], E->stream);

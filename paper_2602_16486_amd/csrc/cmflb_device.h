@@ -292,9 +292,16 @@ template <typename T>
 __device__ __forceinline__ T cmf_ld(const T *p) {
   return *p;
 }
-template <typename T>
+// NT: non-temporal (streaming) store, used when every population row of
+// the buffer is a whole number of cache lines, so a wave writes whole lines;
+// otherwise a plain store, so that the two parts of a line shared by two
+// rows merge in L2 before they go to HBM.
+template <bool NT, typename T>
 __device__ __forceinline__ void cmf_st(T v, T *p) {
-  __builtin_nontemporal_store(v, p);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Population layout in HBM (row-interleaved structure of arrays): the Q
@@ -320,8 +327,9 @@ struct Store<double, R> {
   __device__ __forceinline__ static R load(const double *p, float) {
     return (R)cmf_ld(p);
   }
+  template <bool NT = true>
   __device__ __forceinline__ static void store(double *p, R v, float) {
-    cmf_st((double)v, p);
+    cmf_st<NT>((double)v, p);
   }
 };
 
@@ -331,8 +339,9 @@ struct Store<float, R> {
   __device__ __forceinline__ static R load(const float *p, float) {
     return (R)cmf_ld(p);
   }
+  template <bool NT = true>
   __device__ __forceinline__ static void store(float *p, R v, float) {
-    cmf_st((float)v, p);
+    cmf_st<NT>((float)v, p);
   }
 };
 
@@ -344,9 +353,10 @@ struct Store<__half, R> {
         cmf_ld(reinterpret_cast<const unsigned short *>(p));
     return (R)(__half2float(__ushort_as_half(bits)) * scale);
   }
+  template <bool NT = true>
   __device__ __forceinline__ static void store(__half *p, R v, float iscale) {
     const __half h = __float2half_rn((float)v * iscale);
-    cmf_st(__half_as_ushort(h), reinterpret_cast<unsigned short *>(p));
+    cmf_st<NT>(__half_as_ushort(h), reinterpret_cast<unsigned short *>(p));
   }
 };
 
@@ -359,12 +369,13 @@ struct Store<__hip_bfloat16, R> {
         cmf_ld(reinterpret_cast<const unsigned short *>(p));
     return (R)(__uint_as_float(((unsigned int)bits) << 16) * scale);
   }
+  template <bool NT = true>
   __device__ __forceinline__ static void store(__hip_bfloat16 *p, R v,
                                                float iscale) {
     const __hip_bfloat16 h = __float2bfloat16((float)v * iscale);
     unsigned short bits;
     __builtin_memcpy(&bits, &h, sizeof(bits));
-    cmf_st(bits, reinterpret_cast<unsigned short *>(p));
+    cmf_st<NT>(bits, reinterpret_cast<unsigned short *>(p));
   }
 };
 

@@ -39,7 +39,8 @@ struct ReplicaParams {
   int32_t q, nx, ny, nz;
   int32_t nsites, tile0, ntiles, noise;
   int64_t offset;  // element offset of the replica's populations in an arena
-  uint32_t key0, key1, replica, pad;
+  uint32_t key0, key1, replica;
+  int32_t spt;  // sites per thread: a tile is spt x kEnsembleBlock sites
   R rho0;
   R amp[27];
   R oml[27];
@@ -58,10 +59,11 @@ struct ConvParams {
 enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 // launchers (defined in cmflb_kernels.hip); all return hipError_t
-hipError_t launch_step(int q, int storage, bool general, const void *params,
-                       const void *src, void *dst, const int64_t *step_ptr,
-                       double *partials, int grid, int block,
-                       hipStream_t stream);
+// nt: non-temporal population stores (rows of whole cache lines), else plain
+hipError_t launch_step(int q, int storage, bool general, bool nt,
+                       const void *params, const void *src, void *dst,
+                       const int64_t *step_ptr, double *partials, int grid,
+                       int block, hipStream_t stream);
 hipError_t launch_finalize(const double *partials, int nparts, double *level2,
                            double *series, int cap, int64_t *step_ptr,
                            double mass0, bool stats, hipStream_t stream);
@@ -100,7 +102,18 @@ hipError_t launch_sk_segments(const double *acc, int64_t M, int nx, int ny, int 
 
 // ensemble
 constexpr int kEnsembleBlock = 256;
-hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
+// default sites per thread of an ensemble tile: a D2Q9 site carries a third
+// of the bytes of a D3Q27 one, so its tiles are longer to amortise the
+// per-workgroup start (replica record loads) and the partial-sum reduction
+constexpr int kEnsembleSpt9 = 3, kEnsembleSpt27 = 1;
+// cache-line bytes: a buffer whose population rows are multiples of this
+// gets non-temporal stores
+constexpr int kLineBytes = 128;
+// XCDs of an MI355X (the tile maps assume round-robin dispatch over them)
+constexpr int kXcds = 8;
+// adjacent ensemble tiles kept on one XCD
+constexpr int kXcdChunk = 32;
+hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
                                 const int64_t *step_ptr, double *partials,

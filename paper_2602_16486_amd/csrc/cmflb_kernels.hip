@@ -268,42 +268,90 @@ __device__ __forceinline__ int wrap_sub(int a, int c, int n) {
   return r;
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base pointer: the
+// scalar-base + 32-bit vector-offset form of the global memory instructions.
+template <typename T>
+__device__ __forceinline__ T *at_byte(T *base, uint32_t boff) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ const T *at_byte(const T *base, uint32_t boff) {
+  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+
 // Pull the Q populations of site (x, y, z) of a box (nx, ny, nz) whose
-// buffer starts at src: f_i(x) <- f*_i(x - c_i), periodic.  When y and z are
-// wave-uniform (single lattice) the row part of every address is scalar;
-// the ensemble kernel passes per-lane rows.
-template <class L, typename S, typename R>
+// buffer starts at src: f_i(x) <- f*_i(x - c_i), periodic.
+//
+// LANE_ROWS = false: y and z are wave-uniform (one lattice row per tile), so
+// the row part of every address is scalar.  (Addressing each population row
+// from its own scalar base measured 4% slower here than 64-bit vector
+// addresses: the 27 bases spill scalar registers.)
+// LANE_ROWS = true: every lane may sit in another row (ensemble tiles); the
+// whole offset inside the buffer is one 32-bit byte count from the uniform
+// buffer base (the buffer is below 4 GiB, checked at creation), which saves
+// the per-lane 64-bit address arithmetic.
+template <class L, typename S, typename R, bool LANE_ROWS>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
                                           const float *scale, int nx, int ny,
                                           int nz, int x, int y, int z) {
   using ST = Store<S, R>;
   const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1), (uint32_t)x,
                           (uint32_t)(x == 0 ? nx - 1 : x - 1)};
-  int64_t srow[3][3];
+  if constexpr (!LANE_ROWS) {
+    int64_t srow[3][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int ys = wrap_sub(y, a - 1, ny);
-      const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
-      srow[a][b] = (int64_t)ys + (int64_t)ny * zs;
+      for (int b = 0; b < 3; ++b) {
+        const int ys = wrap_sub(y, a - 1, ny);
+        const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+        srow[a][b] = (int64_t)ys + (int64_t)ny * zs;
+      }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
+      d[i] = ST::load(base + xs[L::cx[i] + 1], scale[i]);
     }
+  } else {
+    constexpr uint32_t B = sizeof(S);
+    const uint32_t unx = (uint32_t)nx, uny = (uint32_t)ny;
+    uint32_t sblk[3][3];  // first element of the Q-row block of each source row
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
-    d[i] = ST::load(base + xs[L::cx[i] + 1], scale[i]);
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const uint32_t ys = (uint32_t)wrap_sub(y, a - 1, ny);
+        const uint32_t zs = L::D == 3 ? (uint32_t)wrap_sub(z, b - 1, nz) : (uint32_t)z;
+        sblk[a][b] = (ys + uny * zs) * (uint32_t)L::Q * unx;
+      }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const uint32_t e = sblk[L::cy[i] + 1][L::cz[i] + 1] + (uint32_t)i * unx + xs[L::cx[i] + 1];
+      d[i] = ST::load(at_byte(src, e * B), scale[i]);
+    }
   }
 }
 
-template <class L, typename S, typename R>
+// Write the Q post-collision populations of site x of lattice row `row`
+// (same two addressing forms as load_site; NT selects the store kind).
+template <class L, typename S, typename R, bool LANE_ROWS, bool NT>
 __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
                                            const float *iscale, int nx, int x,
                                            int64_t row) {
   using ST = Store<S, R>;
+  if constexpr (!LANE_ROWS) {
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    S *base = dst + pop_row_offset<L::Q>(i, row, nx);
-    ST::store(base + (uint32_t)x, d[i], iscale[i]);
+    for (int i = 0; i < L::Q; ++i) {
+      S *base = dst + pop_row_offset<L::Q>(i, row, nx);
+      ST::template store<NT>(base + (uint32_t)x, d[i], iscale[i]);
+    }
+  } else {
+    constexpr uint32_t B = sizeof(S);
+    const uint32_t unx = (uint32_t)nx;
+    const uint32_t blk = (uint32_t)row * (uint32_t)L::Q * unx + (uint32_t)x;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+      ST::template store<NT>(at_byte(dst, (blk + (uint32_t)i * unx) * B), d[i], iscale[i]);
   }
 }
 
@@ -317,7 +365,7 @@ __device__ __forceinline__ TileXY tile_coords(int tile, int nxb, int ny, int bx)
   return TileXY{xb * bx + (int)threadIdx.x, row % ny, row / ny};
 }
 
-template <class L, typename S, typename R, bool GENERAL>
+template <class L, typename S, typename R, bool GENERAL, bool NT>
 __global__ __launch_bounds__(kMaxBlock) void k_step(
     const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
     const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
@@ -333,11 +381,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
     const TileXY c = tile_coords(tile, p.nxb, ny, BX);
     if (c.x < nx) {
       R d[Q];
-      load_site<L, S, R>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+      load_site<L, S, R, false>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL>(d, p, (uint32_t)site, step, acc);
-      store_site<L, S, R>(d, dst, p.iscale, nx, c.x, row);
+      store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
     }
   }
   block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride);
@@ -680,11 +728,11 @@ __global__ __launch_bounds__(256) void k_sk_segments(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 // batched ensemble: one launch per step over the tiles of every replica
 // ---------------------------------------------------------------------------
-// A tile is kEnsembleBlock consecutive sites (x fastest) of one replica, so
-// every lane of a workgroup is busy whatever the box edges; the replica, and
-// with it the lattice type, is uniform per workgroup.  Replicas are listed
-// D3Q27 first (heavier tiles dispatched first).
-template <class L, typename S, typename R, bool GENERAL>
+// A tile is spt x kEnsembleBlock consecutive sites (x fastest) of one
+// replica, so every lane of a workgroup is busy whatever the box edges; the
+// replica, and with it the lattice type, is uniform per workgroup.
+// Replicas are listed D3Q27 first (heavier tiles dispatched first).
+template <class L, typename S, typename R, bool GENERAL, bool NT>
 __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
                                               S *__restrict__ dst,
                                               const ReplicaParams<R> &p,
@@ -697,28 +745,48 @@ __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
   const int y = (int)(row % ny);
   const int z = (int)(row / ny);
   R d[L::Q];
-  load_site<L, S, R>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
+  load_site<L, S, R, true>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
   collide_site<L, R, GENERAL>(d, p, us, step, acc);
-  store_site<L, S, R>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
+  store_site<L, S, R, true, NT>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
 }
 
-template <typename S, typename R, bool GENERAL>
+// Workgroups are handed to the XCDs round-robin by id and every XCD has its
+// own L2.  Map workgroup b to a tile so that runs of kXcdChunk adjacent
+// tiles go to one XCD (chunk c to XCD c mod kXcds): two tiles that split a
+// lattice row, or that pull from each other's rows, then mostly meet in the
+// same L2, which merges the two parts of a shared cache line before it goes
+// to HBM; the chunks rotate over the XCDs, so tiles of different cost (D2Q9
+// and D3Q27 replicas) spread evenly.  A bijection on [0, n): the last
+// n mod (kXcds kXcdChunk) tiles keep their own ids.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int G = kXcds * kXcdChunk;
+  if (b >= n / G * G) return b;
+  const int j = b % kXcds, k = b / kXcds;
+  return ((k / kXcdChunk) * kXcds + j) * kXcdChunk + k % kXcdChunk;
+}
+
+template <typename S, typename R, bool GENERAL, bool NT>
 __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
     const S *__restrict__ src, S *__restrict__ dst,
     const ReplicaParams<R> *__restrict__ reps, const int32_t *__restrict__ tile_rep,
     const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const ReplicaParams<R> &p = reps[tile_rep[tile]];
   const uint32_t step = (uint32_t)*step_ptr;
   Acc acc;
 #pragma unroll
   for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
-  const int64_t s = (int64_t)(tile - p.tile0) * kEnsembleBlock + threadIdx.x;
-  if (s < p.nsites) {
-    if (p.q == 27)
-      ensemble_site<D3Q27, S, R, GENERAL>(src, dst, p, s, step, acc);
-    else
-      ensemble_site<D2Q9, S, R, GENERAL>(src, dst, p, s, step, acc);
+  const int64_t s0 = (int64_t)(tile - p.tile0) * p.spt * kEnsembleBlock + threadIdx.x;
+  if (p.q == 27) {
+    for (int j = 0; j < p.spt; ++j) {
+      const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
+      if (s < p.nsites) ensemble_site<D3Q27, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+    }
+  } else {
+    for (int j = 0; j < p.spt; ++j) {
+      const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
+      if (s < p.nsites) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+    }
   }
   block_store_acc(acc, partials + (int64_t)tile * kPartStride);
 }
@@ -755,43 +823,44 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <class L, typename S, typename R, bool G>
+template <class L, typename S, typename R, bool G, bool NT>
 hipError_t step_one(const void *params, const void *src, void *dst,
                     const int64_t *step_ptr, double *partials, int grid,
                     int block, hipStream_t stream) {
   const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
-  hipLaunchKernelGGL((k_step<L, S, R, G>), dim3(grid), dim3(block), 0, stream,
+  hipLaunchKernelGGL((k_step<L, S, R, G, NT>), dim3(grid), dim3(block), 0, stream,
                      static_cast<const S *>(src), static_cast<S *>(dst), p,
                      step_ptr, partials);
   return hipGetLastError();
 }
 
 template <class L, typename S, typename R>
-hipError_t step_lg(bool general, const void *params, const void *src, void *dst,
-                   const int64_t *step_ptr, double *partials, int grid,
-                   int block, hipStream_t stream) {
-  return general ? step_one<L, S, R, true>(params, src, dst, step_ptr, partials,
-                                           grid, block, stream)
-                 : step_one<L, S, R, false>(params, src, dst, step_ptr,
-                                            partials, grid, block, stream);
+hipError_t step_lg(bool general, bool nt, const void *params, const void *src,
+                   void *dst, const int64_t *step_ptr, double *partials,
+                   int grid, int block, hipStream_t stream) {
+  if (general)
+    return nt ? step_one<L, S, R, true, true>(params, src, dst, step_ptr, partials, grid, block, stream)
+              : step_one<L, S, R, true, false>(params, src, dst, step_ptr, partials, grid, block, stream);
+  return nt ? step_one<L, S, R, false, true>(params, src, dst, step_ptr, partials, grid, block, stream)
+            : step_one<L, S, R, false, false>(params, src, dst, step_ptr, partials, grid, block, stream);
 }
 
 template <class L>
-hipError_t step_l(int storage, bool general, const void *params,
+hipError_t step_l(int storage, bool general, bool nt, const void *params,
                   const void *src, void *dst, const int64_t *step_ptr,
                   double *partials, int grid, int block, hipStream_t stream) {
   switch (storage) {
     case kF64:
-      return step_lg<L, double, double>(general, params, src, dst, step_ptr,
+      return step_lg<L, double, double>(general, nt, params, src, dst, step_ptr,
                                         partials, grid, block, stream);
     case kF32:
-      return step_lg<L, float, float>(general, params, src, dst, step_ptr,
+      return step_lg<L, float, float>(general, nt, params, src, dst, step_ptr,
                                       partials, grid, block, stream);
     case kF16:
-      return step_lg<L, __half, float>(general, params, src, dst, step_ptr,
+      return step_lg<L, __half, float>(general, nt, params, src, dst, step_ptr,
                                        partials, grid, block, stream);
     case kBF16:
-      return step_lg<L, __hip_bfloat16, float>(general, params, src, dst,
+      return step_lg<L, __hip_bfloat16, float>(general, nt, params, src, dst,
                                                step_ptr, partials, grid, block,
                                                stream);
   }
@@ -800,15 +869,15 @@ hipError_t step_l(int storage, bool general, const void *params,
 
 }  // namespace
 
-hipError_t launch_step(int q, int storage, bool general, const void *params,
-                       const void *src, void *dst, const int64_t *step_ptr,
-                       double *partials, int grid, int block,
-                       hipStream_t stream) {
+hipError_t launch_step(int q, int storage, bool general, bool nt,
+                       const void *params, const void *src, void *dst,
+                       const int64_t *step_ptr, double *partials, int grid,
+                       int block, hipStream_t stream) {
   if (q == 9)
-    return step_l<D2Q9>(storage, general, params, src, dst, step_ptr, partials,
-                        grid, block, stream);
+    return step_l<D2Q9>(storage, general, nt, params, src, dst, step_ptr,
+                        partials, grid, block, stream);
   if (q == 27)
-    return step_l<D3Q27>(storage, general, params, src, dst, step_ptr,
+    return step_l<D3Q27>(storage, general, nt, params, src, dst, step_ptr,
                          partials, grid, block, stream);
   return hipErrorInvalidValue;
 }
@@ -966,24 +1035,28 @@ hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
   return hipGetLastError();
 }
 
-hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
+hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
                                 const int64_t *step_ptr, double *partials,
                                 hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  auto go = [&](auto stt, auto rt, auto gt) {
+  auto go = [&](auto stt, auto rt, auto gt, auto ntt) {
     using S = typename decltype(stt)::type;
     using R = typename decltype(rt)::type;
     constexpr bool G = decltype(gt)::value;
-    hipLaunchKernelGGL((k_ensemble_step<S, R, G>), dim3(ntiles), dim3(kEnsembleBlock), 0,
+    constexpr bool NT = decltype(ntt)::value;
+    hipLaunchKernelGGL((k_ensemble_step<S, R, G, NT>), dim3(ntiles), dim3(kEnsembleBlock), 0,
                        stream, static_cast<const S *>(src), static_cast<S *>(dst),
                        static_cast<const ReplicaParams<R> *>(reps), tile_rep, step_ptr,
                        partials);
     return hipGetLastError();
   };
+  auto by_nt = [&](auto stt, auto rt, auto gt) {
+    return nt ? go(stt, rt, gt, std::true_type{}) : go(stt, rt, gt, std::false_type{});
+  };
   auto by_general = [&](auto stt, auto rt) {
-    return general ? go(stt, rt, std::true_type{}) : go(stt, rt, std::false_type{});
+    return general ? by_nt(stt, rt, std::true_type{}) : by_nt(stt, rt, std::false_type{});
   };
   switch (storage) {
     case kF64: return by_general(Tag<double>{}, Tag<double>{});

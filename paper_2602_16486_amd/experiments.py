@@ -186,7 +186,7 @@ def config5(scale):
         ens.step(steps)
         ens.synchronize()
         secs = time.perf_counter() - t0
-        ratios, bands, inband = [], [], 0
+        ratios, bands, inband, outliers = [], [], 0, []
         for k, r in enumerate(manifest):
             st = ens.stats(k, cap=steps, raise_nonfinite=False)
             dims = 2 if r["q"] == 9 else 3
@@ -201,11 +201,15 @@ def config5(scale):
                     + 9 * r["kT"] / r["rho0"] + (1 / (8 * math.pi * nu * steps / 2) if dims == 2 else 0))
             ratios.append(ratio)
             bands.append(band)
-            inband += abs(ratio - 1) <= band
+            if abs(ratio - 1) <= band:
+                inband += 1
+            else:
+                outliers.append({"index": k, "q": r["q"], "shape": list(r["shape"]), "kT": r["kT"],
+                                 "tau": r["tau"], "ratio": ratio, "band": band})
     _emit({"experiment": "config5", "replicas": len(manifest), "steps": steps, "seconds": secs,
            "u2_over_target_median": float(np.median(ratios)),
            "u2_over_target_min_max": [float(min(ratios)), float(max(ratios))],
-           "replicas_within_band": int(inband)})
+           "replicas_within_band": int(inband), "outside_band": outliers})
 
 
 EXPERIMENTS = {f.__name__: f for f in (test3, test4, test5, test6, test7, config2, config3, config4, config5)}

@@ -59,6 +59,30 @@ def test_replicas_match_standalone_lattices(storage):
         assert np.allclose(st[k], ref_st, rtol=1e-12, atol=1e-18), f"replica {k} statistics"
 
 
+@pytest.mark.parametrize("spt9,spt27", [("1", "3"), ("7", "2")])
+def test_tile_lengths_do_not_change_results(monkeypatch, spt9, spt27):
+    """Sites per thread of the ensemble tiles (a launch-shape choice) leave
+    every population bit-identical."""
+    states = [_state(r, 400 + k) for k, r in enumerate(REPLICAS)]
+    out = []
+    for env in ({}, {"CMF_ENSEMBLE_SPT9": spt9, "CMF_ENSEMBLE_SPT27": spt27}):
+        for key in ("CMF_ENSEMBLE_SPT9", "CMF_ENSEMBLE_SPT27"):
+            monkeypatch.delenv(key, raising=False)
+        for key, val in env.items():
+            monkeypatch.setenv(key, val)
+        with Ensemble(REPLICAS, storage="f32") as ens:
+            for k, f in enumerate(states):
+                ens.set_populations(k, f)
+            ens.step(9)
+            out.append(([ens.get_populations(k) for k in range(len(REPLICAS))],
+                        [ens.stats(k) for k in range(len(REPLICAS))], ens.info["tiles"]))
+    assert out[0][2] != out[1][2]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-18)
+
+
 def test_replica_matches_oracle():
     r = REPLICAS[3]
     f0 = _state(r, 7)
