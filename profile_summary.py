@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402  (kernel_source_hash, constants)
 
-STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false>"
+STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false, true>"
 COPY_KERNEL = "cmf::cmf_stream_copy_kernel"
 N = 256 ** 3
 ALG_BYTES = 2 * 27 * 4 * N
@@ -129,5 +129,55 @@ def main(outdir):
     print("\n".join(lines))
 
 
+ENS_KERNEL = "void cmf::k_ensemble_step<float, float, false, false>"
+CMD_ENS = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_ens -o ens --output-format csv "
+           "-- python3 bench.py --steps 50 --warmup 16 --variants \"\" --no-cpu --no-tune")
+
+
+def ensemble_summary(outdir):
+    """profiles/k_ensemble_step_mixed320.md from the kernel trace of a bench
+    run with the ensemble leg (prof_ens/, prof_ens.json)."""
+    path = os.path.join(outdir, "prof_ens", "ens_kernel_stats.csv")
+    if not os.path.exists(path):
+        return
+    stats = {r["Name"]: r for r in csv.DictReader(open(path))}
+    ens = next(v for k, v in stats.items() if k.startswith(ENS_KERNEL))
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            for r in csv.DictReader(open(os.path.join(outdir, "prof_ens", "ens_kernel_trace.csv")))
+            if r["Kernel_Name"].startswith(ENS_KERNEL)]
+    line = json.loads(open(os.path.join(outdir, "prof_ens.json")).read().strip().splitlines()[-1])
+    e = line["ensemble"]
+    alg = e["bytes_per_step"]
+    med = statistics.median(durs)
+    lines = [
+        "# k_ensemble_step<f32> on the mixed ensemble (256 D2Q9 + 64 D3Q27 replicas) — rocprofv3 summary",
+        "",
+        f"Workload: {e['replicas']} replicas, {e['sites']} sites, {alg} algorithmic bytes per step "
+        "(2 Q 4 B per site, summed over the replicas).",
+        "",
+        "Command (repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`):",
+        "",
+        "    " + CMD_ENS,
+        "    python profile_summary.py gpurun_out",
+        "",
+        "| kernel | calls | average ns | min ns | max ns |",
+        "|---|---|---|---|---|",
+    ]
+    for k, v in sorted(stats.items(), key=lambda kv: -float(kv[1]["TotalDurationNs"]))[:12]:
+        lines.append(f"| `{k[:90]}` | {v['Calls']} | {float(v['AverageNs']):.0f} | {v['MinNs']} | {v['MaxNs']} |")
+    lines += [
+        "",
+        f"Ensemble step kernel: {float(ens['AverageNs']) / 1e6:.4f} ms average, {med / 1e6:.4f} ms median over "
+        f"{len(durs)} dispatches (bench.py's HIP-event figure: {e['kernel_ms']:.4f} ms); "
+        f"{alg / (med * 1e-9) / 1e9:.0f} GB/s algorithmic = {alg / (med * 1e-9) / 8e12:.3f} of 8 TB/s, "
+        f"{e['sites'] / (med * 1e-9) / 1e9:.1f} GLUPS.",
+        "",
+    ]
+    with open(os.path.join(ROOT, "profiles", "k_ensemble_step_mixed320.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     main(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")
+    ensemble_summary(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")
