@@ -32,7 +32,8 @@
  *    memory allocated by cmf_create is owned by the lattice and released by
  *    cmf_destroy.
  *  - Steps are enqueued asynchronously on the HIP stream given at creation
- *    (NULL = the null stream); every call that returns host data
+ *    (NULL: the lattice creates a stream of its own, default priority, and
+ *    destroys it with the lattice); every call that returns host data
  *    synchronises that stream first.
  */
 #ifndef CMFLB_H
@@ -115,7 +116,8 @@ int cmf_device_count(void);
  * sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2) of eq. phi_general, storage
  * scales) and allocates two population buffers of q x N elements of the
  * storage type plus statistics scratch.  The populations start at rest
- * (f = w rho0) at step 0.  `hip_stream` is a hipStream_t or NULL.
+ * (f = w rho0) at step 0.  `hip_stream` is a hipStream_t, or NULL for a
+ * stream owned by the lattice.
  * Errors: CMF_EINVAL (bad sizes, tau < 0.5, kT < 0, rho0 <= 0, rates out of
  * [0, 2], N >= 2^31, nx >= 2^28), CMF_ENOMEM, CMF_EHIP. */
 int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
@@ -208,6 +210,13 @@ int cmf_stats(cmf_lattice *lat, cmf_moments *out, int64_t cap,
  * u_x block first).  Either pointer may be NULL.  Asynchronous on the
  * lattice's stream. */
 int cmf_sample_macro(cmf_lattice *lat, void *rho_dev, void *u_dev);
+
+/* The density and velocity of the current pre-collision state, computed on
+ * the device in FP64 from the stored populations (eq. macro: rho = sum f,
+ * rho u = sum c f): rho (N host doubles) and u (3 x N host doubles, u_x
+ * block first; u_z = 0 on D2Q9).  Either pointer may be NULL.  Allocates a
+ * temporary device buffer of 4 N doubles.  Synchronous. */
+int cmf_get_macro(cmf_lattice *lat, double *rho, double *u);
 
 /* Diagnostic: the standard normals eta_v the step kernels draw, for the
  * noisy modes of `n` consecutive sites starting at `site0` of step `step`.

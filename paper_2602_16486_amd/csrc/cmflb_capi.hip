@@ -907,6 +907,23 @@ int cmf_sample_macro(cmf_lattice *L, void *rho_dev, void *u_dev) {
   return CMF_OK;
 }
 
+int cmf_get_macro(cmf_lattice *L, double *rho, double *u) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (!rho && !u) return CMF_OK;
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  double *d = nullptr;
+  const size_t bytes = sizeof(double) * 4 * L->N;
+  if (hipMalloc((void **)&d, bytes) != hipSuccess)
+    return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  hipError_t e = launch_macro(L->q, L->storage, L->cp, L->buf[L->parity], d, d + L->N, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e == hipSuccess && rho) e = hipMemcpy(rho, d, sizeof(double) * L->N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && u) e = hipMemcpy(u, d + L->N, sizeof(double) * 3 * L->N, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(CMF_EHIP, "get_macro failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
 int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step, int64_t site0,
                      int64_t n, int32_t fp64, double *out) {
   if (q != 9 && q != 27) return fail(CMF_EINVAL, "q must be 9 or 27");

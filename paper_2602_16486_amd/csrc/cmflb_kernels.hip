@@ -545,11 +545,11 @@ __global__ __launch_bounds__(256) void k_gather(const ConvParams cp,
                  cp.scale[i]);
 }
 
-template <class L, typename S>
+template <class L, typename S, typename T>
 __global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
                                                const S *__restrict__ buf,
-                                               float *__restrict__ rho_out,
-                                               float *__restrict__ u_out) {
+                                               T *__restrict__ rho_out,
+                                               T *__restrict__ u_out) {
   using ST = Store<S, double>;
   const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -566,11 +566,11 @@ __global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
     j[2] += L::cz[i] * d;
   }
   const double rho = cp.rho0 + drho;
-  if (rho_out) rho_out[s] = (float)rho;
+  if (rho_out) rho_out[s] = (T)rho;
   if (u_out) {
-    u_out[s] = (float)(j[0] / rho);
-    u_out[N + s] = (float)(j[1] / rho);
-    u_out[2 * N + s] = (float)(j[2] / rho);
+    u_out[s] = (T)(j[0] / rho);
+    u_out[N + s] = (T)(j[1] / rho);
+    u_out[2 * N + s] = (T)(j[2] / rho);
   }
 }
 
@@ -976,17 +976,29 @@ hipError_t launch_gather(int q, int storage, const ConvParams &cp,
   });
 }
 
-hipError_t launch_macro(int q, int storage, const ConvParams &cp,
-                        const void *buf, float *rho, float *u,
-                        hipStream_t stream) {
+template <typename T>
+hipError_t macro_t(int q, int storage, const ConvParams &cp, const void *buf, T *rho,
+                   T *u, hipStream_t stream) {
   const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
   return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
     using L = typename decltype(lt)::type;
     using S = typename decltype(stt)::type;
-    hipLaunchKernelGGL((k_macro<L, S>), dim3(blocks_for(N, 256)), dim3(256), 0,
+    hipLaunchKernelGGL((k_macro<L, S, T>), dim3(blocks_for(N, 256)), dim3(256), 0,
                        stream, cp, static_cast<const S *>(buf), rho, u);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_macro(int q, int storage, const ConvParams &cp,
+                        const void *buf, float *rho, float *u,
+                        hipStream_t stream) {
+  return macro_t<float>(q, storage, cp, buf, rho, u, stream);
+}
+
+hipError_t launch_macro(int q, int storage, const ConvParams &cp,
+                        const void *buf, double *rho, double *u,
+                        hipStream_t stream) {
+  return macro_t<double>(q, storage, cp, buf, rho, u, stream);
 }
 
 hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,

@@ -4,7 +4,8 @@ synthetic rest-state inputs.  Each run prints one JSON line.
 
     python -m paper_2602_16486_amd.experiments NAME [--scale S]
 
-NAME: test3 test4 test5 test6 test7 config2 config3 config4 config5, or all.
+NAME: test2 tg3d test3 test4 test5 test6 test7 config2 config3 config4 config5, or
+all.
 --scale multiplies the number of steps (default 1; the paper's durations
 are used at scale 1 where they are stated).
 """
@@ -85,6 +86,59 @@ def run(q, shape, storage="f32", steps=1000, tau=0.8, kT=1e-4, rho0=1.0, seed=1,
         out["S_rho_max_dev"] = float(np.abs(sr[big] - 1).max())
         out["S_u_shells"] = su.round(5).tolist()
     return out
+
+
+def _tg_run(q, shape, storage, tau, lam, u0, checkpoints):
+    """Taylor-Green vortex (kT = 0) stepped on the GPU; returns the initial
+    velocity and the velocity field at each checkpoint step."""
+    u = W.taylor_green(shape, u0)
+    out, done = [], 0
+    with Lattice(q, shape, storage=storage, tau=tau, kT=0.0, lam=lam, flags=2) as lat:
+        lat.init_equilibrium(u=u)
+        for t in checkpoints:
+            lat.step(t - done)
+            done = t
+            out.append(lat.macroscopic()[1])
+    return u, out
+
+
+def test2(scale):
+    """Test 2 (Sec. 3, Fig. 1): Taylor-Green decay at Re = u0 N_y / nu =
+    1000, u0 = 1e-3, kT = 0, for one convective time N_y / u0 (the paper
+    gives no end time); L2 velocity error against exp(-2 nu kappa^2 t) for
+    N = 16 ... 256 and the fitted slope, FP64 and FP32 storage."""
+    u0 = 1e-3
+    for storage in ("f64", "f32"):
+        sizes, errs = [], []
+        t0 = time.perf_counter()
+        for n in (16, 32, 64, 128, 256):
+            nu = u0 * n / 1000.0
+            steps = int(round(n / u0 * scale))
+            u, (un,) = _tg_run(9, (n, n), storage, 0.5 + 3 * nu, None, u0, [steps])
+            ua = u[:2] * math.exp(-2 * nu * (2 * math.pi / n) ** 2 * steps)
+            sizes.append(n)
+            errs.append(float(np.linalg.norm(un[:2] - ua) / np.linalg.norm(ua)))
+        slope = float(np.polyfit(np.log(sizes), np.log(errs), 1)[0])
+        _emit({"experiment": "test2", "storage": storage, "sizes": sizes, "l2_error": errs,
+               "fitted_slope": slope, "seconds": time.perf_counter() - t0})
+
+
+def tg3d(scale):
+    """The viscosity of the D3Q27 rate readings: the Test 2 vortex in the
+    x-y plane of a 48 x 48 x 2 box, decay rate fitted between steps 48 and
+    192, for the paper's rates (diagonal second-order modes at 1) and the
+    isotropic ones (all second-order modes at omega)."""
+    from .lattice import rate_vector
+    n = 48
+    kappa = 2 * math.pi / n
+    t1, t2 = int(48 * scale), int(192 * scale)
+    for tau in (0.55, 0.6, 0.8, 1.0, 1.2, 2.0):
+        for kind in ("paper", "isotropic"):
+            u, (a, b) = _tg_run(27, (n, n, 2), "f64", tau, rate_vector(27, tau, kind), 1e-3, [t1, t2])
+            amp = [float((x[:2] * u[:2]).sum() / (u[:2] ** 2).sum()) for x in (a, b)]
+            nu = math.log(amp[0] / amp[1]) / (2 * kappa ** 2 * (t2 - t1))
+            _emit({"experiment": "tg3d", "tau": tau, "rates": kind, "nu_fit": nu,
+                   "nu_shear": (tau - 0.5) / 3, "nu_unit_rate": 1 / 6})
 
 
 def test3(scale):
@@ -215,7 +269,8 @@ def config5(scale):
            "replicas_within_band": int(inband), "outside_band": outliers})
 
 
-EXPERIMENTS = {f.__name__: f for f in (test3, test4, test5, test6, test7, config2, config3, config4, config5)}
+EXPERIMENTS = {f.__name__: f for f in (test2, tg3d, test3, test4, test5, test6, test7, config2, config3, config4,
+                                        config5)}
 
 
 def main(argv=None):

@@ -9,6 +9,34 @@ import numpy as np
 from . import _lib
 
 
+def rate_vector(q, tau, kind="paper"):
+    """Per-mode relaxation rates Lambda_v, in the mode order of the paper's
+    bases (Sec. 2.2 for D2Q9, Sec. 2.3 for D3Q27), omega = 1 / tau.
+
+    * ``paper``: the printed rates -- D2Q9 Lambda_4 = Lambda_5 = omega, D3Q27
+      Lambda_7..9 = omega, every other mode 1.  On D3Q27 the diagonal
+      second-order modes (4..6) then relax at 1, so normal-stress differences
+      diffuse with nu = c_s^2 (1 - 1/2) = 1/6 whatever tau is, and only the
+      off-diagonal shear follows c_s^2 (tau - 1/2).
+    * ``isotropic``: D3Q27 with Lambda_4..9 = omega (one shear viscosity for
+      every second-order mode, bulk included); on D2Q9 the paper's rates,
+      which are already isotropic.
+    * ``single``: Lambda_v = omega for every mode (single-rate comparator of
+      Test 6).
+    """
+    omega = 1.0 / float(tau)
+    lam = np.ones(int(q))
+    if kind == "single":
+        lam[:] = omega
+    elif kind == "paper" or (kind == "isotropic" and q == 9):
+        lam[[4, 5] if q == 9 else [7, 8, 9]] = omega
+    elif kind == "isotropic":
+        lam[4:10] = omega
+    else:
+        raise ValueError(f"unknown rate kind {kind!r}")
+    return lam
+
+
 class Lattice:
     """A periodic D2Q9 or D3Q27 box stepped by the fused CM-FLBM kernel.
 
@@ -81,6 +109,14 @@ class Lattice:
         f = np.zeros((self.q, self.n))
         _lib.check(self._lib.cmf_get_populations(self._h, _lib._d(f)))
         return f
+
+    def macroscopic(self):
+        """(rho, u) of the current pre-collision state, FP64 from the device:
+        rho shape (N,), u shape (3, N)."""
+        rho = np.zeros(self.n)
+        u = np.zeros((3, self.n))
+        _lib.check(self._lib.cmf_get_macro(self._h, _lib._d(rho), _lib._d(u)))
+        return rho, u
 
     def gather_sites(self, sites):
         s = np.ascontiguousarray(sites, dtype=np.int64)

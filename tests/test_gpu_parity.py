@@ -312,3 +312,22 @@ def test_full_size_d3q27_256_sampled_one_step():
         worst = max(worst, np.abs(got - fs).max() / np.abs(fs - w).max())
     print(f"256^3 sampled one-step rel err {worst:.3e}")
     assert worst < F32_TOL(1)
+
+
+@pytest.mark.parametrize("q,shape,storage", [(9, (19, 7), "f64"), (27, (9, 6, 5), "f64"), (27, (9, 6, 5), "f32")])
+def test_get_macro_matches_populations(q, shape, storage):
+    """cmf_get_macro: rho = sum f and u = sum c f / rho of the pre-collision
+    state (eq. macro), in FP64 on the device."""
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, 21, umax=0.04, dims=2 if q == 9 else 3)
+    f = O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, 22, 5e-4)
+    with Lattice(q, shape, storage=storage, kT=1e-4) as lat:
+        lat.set_populations(f)
+        lat.step(3)
+        g = lat.get_populations()
+        r, uu = lat.macroscopic()
+    c, _ = O.lattice(q)
+    rho_ref = g.sum(axis=0)
+    u_ref = (c.T @ g) / rho_ref
+    assert np.allclose(r, rho_ref, rtol=1e-14, atol=0)
+    assert np.abs(uu - u_ref).max() <= 1e-14

@@ -169,3 +169,79 @@ def test_taylor_green_second_order():
     slope1 = math.log(e16 / e32, 2)
     slope2 = math.log(e32 / e64, 2)
     assert 1.7 < slope1 < 2.3 and 1.7 < slope2 < 2.3
+
+
+def _tg_paper_setting(n, basis=0, re=1000.0, u0=1e-3):
+    """Test 2 as the paper sets it up: Re = u0 N_y / nu = 1000, u0 = 1e-3,
+    kT = 0; run for one convective time N_y / u0 (the paper gives no end
+    time).  Returns (populations, relative L2 velocity error)."""
+    q, shape = 9, (n, n)
+    nu = u0 * n / re
+    tau = 0.5 + 3.0 * nu
+    kappa = 2 * math.pi / n
+    u = W.taylor_green(shape, u0)
+    f = O.init_equilibrium(q, n * n, rho0=1.0, u=u)
+    steps = int(round(n / u0))
+    O.run(q, shape, f, 0.0, O.paper_lambda(q, 1 / tau), seed=0, nsteps=steps, basis=basis)
+    c, _ = O.lattice(q)
+    un = (c[:, :2].T @ f) / f.sum(axis=0)
+    ua = u[:2] * math.exp(-2 * nu * kappa ** 2 * steps)
+    return f, np.linalg.norm(un - ua) / np.linalg.norm(ua)
+
+
+def test_taylor_green_paper_setting_second_order_both_bases():
+    """Test 2 (Sec. 3, Fig. 1): second-order convergence at Re = 1000, and the
+    non-orthogonal basis gives the same populations as the orthogonal one
+    when the noise is off."""
+    runs = [_tg_paper_setting(n) for n in (8, 16, 32)]
+    err = [e for _, e in runs]
+    for a, b in zip(err, err[1:]):
+        assert 1.9 < math.log(a / b, 2) < 2.1
+    f_no, e_no = _tg_paper_setting(16, basis=1)
+    f_o = runs[1][0]
+    # two FP64 algorithms: at most one rounding of the populations per step
+    # apart (16000 steps)
+    assert np.abs(f_no - f_o).max() <= 16000 * 2.0 ** -52 * np.abs(f_o).max()
+    assert abs(e_no - err[1]) <= 1e-6 * err[1]
+
+
+def _tg3_viscosity(n, tau, lam, t1=20, t2=80):
+    """Decay rate of the Test 2 vortex (in the x-y plane of a D3Q27 box,
+    kT = 0) fitted between steps t1 and t2 by projection on the initial
+    field, as a kinematic viscosity."""
+    q, shape = 27, (n, n, 2)
+    kappa = 2 * math.pi / n
+    u = W.taylor_green(shape, 1e-3)
+    f = O.init_equilibrium(q, 2 * n * n, rho0=1.0, u=u)
+    c, _ = O.lattice(q)
+    amp, done = [], 0
+    for t in (t1, t2):
+        O.run(q, shape, f, 0.0, lam, seed=0, step0=done, nsteps=t - done)
+        done = t
+        un = (c.T @ f) / f.sum(axis=0)
+        amp.append((un[:2] * u[:2]).sum() / (u[:2] ** 2).sum())
+    return math.log(amp[0] / amp[1]) / (2 * kappa ** 2 * (t2 - t1)), f
+
+
+def test_d3q27_taylor_green_viscosity_of_the_rate_readings():
+    """The axis-aligned vortex has no off-diagonal strain, so its decay is
+    set by the diagonal second-order modes.  Literal D3Q27 rates (Sec. 2.3:
+    Lambda_4-6 = 1, only 7-9 at omega): nu = c_s^2 (1 - 1/2) = 1/6 for every
+    tau, with populations independent of tau up to O(u0^2); isotropic rates
+    (Lambda_4-9 = omega):
+    nu = c_s^2 (tau - 1/2).  (Chapman-Enskog: nu = c_s^2 (1/Lambda - 1/2).)"""
+    fs = []
+    for tau in (0.6, 0.8, 1.2):
+        lam = O.paper_lambda(27, 1 / tau)
+        nu, f = _tg3_viscosity(24, tau, lam)
+        assert abs(nu * 6 - 1) < 0.01
+        fs.append(f)
+        lam_iso = lam.copy()
+        lam_iso[4:10] = 1 / tau
+        nu_iso, _ = _tg3_viscosity(24, tau, lam_iso)
+        assert abs(nu_iso / ((tau - 0.5) / 3) - 1) < 0.02
+    # tau enters only through the off-diagonal modes, which this flow excites
+    # at second order in u0 (1e-3) only
+    _, w = O.lattice(27)
+    for f in fs[1:]:
+        assert np.abs(f - fs[0]).max() <= 1e-5 * np.abs(fs[0] - w[:, None]).max()
