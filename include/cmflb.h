@@ -218,6 +218,21 @@ int cmf_sample_macro(cmf_lattice *lat, void *rho_dev, void *u_dev);
  * temporary device buffer of 4 N doubles.  Synchronous. */
 int cmf_get_macro(cmf_lattice *lat, double *rho, double *u);
 
+/* Velocity statistics of the current pre-collision state (Test 7, Fig. 8),
+ * per component a = x, y, z, with u = sum c f / rho in FP64 per site:
+ *   moments[4 a + 0..3] = mean, variance (1/N), skewness m3 / var^1.5 and
+ *   kurtosis m4 / var^2 (3 for a Gaussian) -- central moments about the mean;
+ *   counts[(nbins + 2) a + b] = histogram of x = (u_a - mean_a) / sqrt(var_a):
+ *   b = 0 counts x < -xmax and non-finite x, b = 1..nbins split [-xmax, xmax)
+ *   into equal bins, b = nbins + 1 counts x >= xmax (z entries are zero on
+ *   D2Q9).  moments (12 doubles) or counts (3 (nbins + 2) int64) may be NULL.
+ * Three device passes (means, central moments, histogram), fixed-order FP64
+ * sums and integer counts; allocates temporary device buffers.
+ * Errors: CMF_EINVAL (nbins outside [1, 4096] or xmax <= 0 with counts).
+ * Synchronous. */
+int cmf_velocity_pdf(cmf_lattice *lat, int32_t nbins, double xmax, double *moments,
+                     int64_t *counts);
+
 /* Diagnostic: the standard normals eta_v the step kernels draw, for the
  * noisy modes of `n` consecutive sites starting at `site0` of step `step`.
  * out: n x q host doubles, zero on the conserved modes.  `fp64` selects

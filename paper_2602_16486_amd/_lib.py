@@ -104,6 +104,7 @@ def load():
     lib.cmf_stats.argtypes = [vp, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_sample_macro.argtypes = [vp, vp, vp]
     lib.cmf_get_macro.argtypes = [vp, _dp, _dp]
+    lib.cmf_velocity_pdf.argtypes = [vp, i32, ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_noise_sample.argtypes = [i32, u64, u32, u32, i64, i64, i32, _dp]
     lib.cmf_philox_words.argtypes = [ctypes.POINTER(ctypes.c_uint32), i64, u32, u32,
                                      ctypes.POINTER(ctypes.c_uint32)]
@@ -135,7 +136,8 @@ def load():
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cmf_get_launch", "cmf_set_launch", "cmf_autotune", "cmf_stream_copy", "cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
                  "cmf_get_populations", "cmf_gather_sites", "cmf_step", "cmf_synchronize",
-                 "cmf_get_step", "cmf_stats", "cmf_sample_macro", "cmf_get_macro", "cmf_noise_sample",
+                 "cmf_get_step", "cmf_stats", "cmf_sample_macro", "cmf_get_macro", "cmf_velocity_pdf",
+                 "cmf_noise_sample",
                  "cmf_philox_words", "cmf_device_count", "cmf_profile_steps"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

@@ -924,6 +924,79 @@ int cmf_get_macro(cmf_lattice *L, double *rho, double *u) {
   return CMF_OK;
 }
 
+int cmf_velocity_pdf(cmf_lattice *L, int32_t nbins, double xmax, double *moments,
+                     int64_t *counts) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (counts && (nbins < 1 || nbins > kVelMaxBins))
+    return fail(CMF_EINVAL, "nbins = %d outside [1, %d]", nbins, kVelMaxBins);
+  if (counts && !(xmax > 0.0 && isfinite(xmax))) return fail(CMF_EINVAL, "xmax must be > 0");
+  if (!moments && !counts) return CMF_OK;
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  const int grid = (int)std::min<int64_t>((L->N + 255) / 256, 1024);
+  const int nb2 = nbins + 2;
+  double *partials = nullptr, *sums = nullptr;
+  unsigned long long *dcounts = nullptr;
+  if (hipMalloc((void **)&partials, sizeof(double) * kVelCols * grid) != hipSuccess ||
+      hipMalloc((void **)&sums, sizeof(double) * kVelCols) != hipSuccess ||
+      (counts && hipMalloc((void **)&dcounts, sizeof(unsigned long long) * 3 * nb2) != hipSuccess)) {
+    if (partials) (void)hipFree(partials);
+    if (sums) (void)hipFree(sums);
+    return fail(CMF_ENOMEM, "hipMalloc failed");
+  }
+  const double n = (double)L->N;
+  double h[kVelCols];
+  // pass 1: the means; pass 2: central moments about them; pass 3: histogram
+  VelNorm c = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double mean[3], var[3], m3[3], m4[3];
+  hipError_t e = launch_vel_moments(L->q, L->storage, L->cp, L->buf[L->parity], c, grid,
+                                    partials, sums, L->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e == hipSuccess) {
+    for (int a = 0; a < 3; ++a) c.centre[a] = mean[a] = h[4 * a] / n;
+    e = launch_vel_moments(L->q, L->storage, L->cp, L->buf[L->parity], c, grid, partials, sums,
+                           L->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e == hipSuccess) {
+    for (int a = 0; a < 3; ++a) {
+      // central moments about the FP64 mean; the residual first moment
+      // d = sum (u - mean) / N corrects them to the exact mean
+      const double d = h[4 * a] / n, s2 = h[4 * a + 1] / n, s3 = h[4 * a + 2] / n,
+                   s4 = h[4 * a + 3] / n;
+      var[a] = s2 - d * d;
+      m3[a] = s3 - 3.0 * d * s2 + 2.0 * d * d * d;
+      m4[a] = s4 - 4.0 * d * s3 + 6.0 * d * d * s2 - 3.0 * d * d * d * d;
+      mean[a] += d;
+      c.centre[a] = mean[a];
+      c.inv_sigma[a] = var[a] > 0.0 ? 1.0 / sqrt(var[a]) : 0.0;
+    }
+    if (moments)
+      for (int a = 0; a < 3; ++a) {
+        moments[4 * a] = mean[a];
+        moments[4 * a + 1] = var[a];
+        moments[4 * a + 2] = var[a] > 0.0 ? m3[a] / (var[a] * sqrt(var[a])) : 0.0;
+        moments[4 * a + 3] = var[a] > 0.0 ? m4[a] / (var[a] * var[a]) : 0.0;
+      }
+  }
+  if (e == hipSuccess && counts) {
+    e = launch_zero_i64(reinterpret_cast<int64_t *>(dcounts), 3 * nb2, L->stream);
+    if (e == hipSuccess)
+      e = launch_vel_hist(L->q, L->storage, L->cp, L->buf[L->parity], c, grid, nbins, xmax,
+                          dcounts, L->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(counts, dcounts, sizeof(unsigned long long) * 3 * nb2,
+                         hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  }
+  (void)hipFree(partials);
+  (void)hipFree(sums);
+  if (dcounts) (void)hipFree(dcounts);
+  if (e != hipSuccess) return fail(CMF_EHIP, "velocity_pdf failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
 int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step, int64_t site0,
                      int64_t n, int32_t fp64, double *out) {
   if (q != 9 && q != 27) return fail(CMF_EINVAL, "q must be 9 or 27");

@@ -92,6 +92,20 @@ hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
                               hipStream_t stream);
 
+// velocity statistics (moments about a centre, normalised histograms)
+constexpr int kVelCols = 12;      // sum (u_a - c_a)^p, column 4 a + p - 1
+constexpr int kVelMaxBins = 4096;
+struct VelNorm {
+  double centre[3];
+  double inv_sigma[3];
+};
+hipError_t launch_vel_moments(int q, int storage, const ConvParams &cp, const void *buf,
+                              const VelNorm &c, int grid, double *partials, double *out,
+                              hipStream_t stream);
+hipError_t launch_vel_hist(int q, int storage, const ConvParams &cp, const void *buf,
+                           const VelNorm &c, int grid, int nbins, double xmax,
+                           unsigned long long *counts, hipStream_t stream);
+
 // structure factor
 hipError_t launch_macro_dev(int q, int storage, const ConvParams &cp,
                             const void *buf, float *out, hipStream_t stream);

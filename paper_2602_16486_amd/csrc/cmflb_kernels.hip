@@ -726,6 +726,126 @@ __global__ __launch_bounds__(256) void k_sk_segments(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// velocity statistics of the pre-collision state (Test 7, Fig. 8): moments
+// about a given centre and normalised histograms, FP64 per site
+// ---------------------------------------------------------------------------
+template <class L, typename S>
+__device__ __forceinline__ void site_velocity(const ConvParams &cp,
+                                              const S *__restrict__ buf,
+                                              int64_t s, double u[3]) {
+  using ST = Store<S, double>;
+  double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const double d = ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+                              cp.scale[i]);
+    drho += d;
+    j[0] += L::cx[i] * d;
+    j[1] += L::cy[i] * d;
+    j[2] += L::cz[i] * d;
+  }
+  const double rho = cp.rho0 + drho;
+  u[0] = j[0] / rho;
+  u[1] = j[1] / rho;
+  u[2] = j[2] / rho;
+}
+
+// per-block sums of (u_a - c_a)^p, p = 1..4, a = x, y, z (column 4 a + p - 1),
+// each block over a fixed set of sites in a fixed order
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_vel_moments(const ConvParams cp,
+                                                     const S *__restrict__ buf,
+                                                     const VelNorm c,
+                                                     double *__restrict__ partials) {
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  double acc[kVelCols];
+#pragma unroll
+  for (int k = 0; k < kVelCols; ++k) acc[k] = 0.0;
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    double u[3];
+    site_velocity<L, S>(cp, buf, s, u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double v = u[a] - c.centre[a], v2 = v * v;
+      acc[4 * a] += v;
+      acc[4 * a + 1] += v2;
+      acc[4 * a + 2] += v2 * v;
+      acc[4 * a + 3] += v2 * v2;
+    }
+  }
+  __shared__ double sh[256][kVelCols];
+#pragma unroll
+  for (int k = 0; k < kVelCols; ++k) sh[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int k = 0; k < kVelCols; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + h][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < kVelCols) partials[(int64_t)blockIdx.x * kVelCols + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// one workgroup: fixed-order sum of the block rows
+__global__ __launch_bounds__(256) void k_vel_moments_final(const double *__restrict__ partials,
+                                                           int nparts, double *__restrict__ out) {
+  __shared__ double sh[256][kVelCols];
+  double acc[kVelCols];
+#pragma unroll
+  for (int k = 0; k < kVelCols; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256)
+#pragma unroll
+    for (int k = 0; k < kVelCols; ++k) acc[k] += partials[(int64_t)b * kVelCols + k];
+#pragma unroll
+  for (int k = 0; k < kVelCols; ++k) sh[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int k = 0; k < kVelCols; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + h][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < kVelCols) out[threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// histogram of x = (u_a - centre_a) / sigma_a: bin 0 counts x < -xmax (and
+// non-finite x), bins 1..nbins split [-xmax, xmax) evenly, bin nbins + 1
+// counts x >= xmax; LDS counters per block, integer totals (order-free)
+template <class L, typename S>
+__global__ __launch_bounds__(256) void k_vel_hist(const ConvParams cp,
+                                                  const S *__restrict__ buf,
+                                                  const VelNorm c, int dims, int nbins,
+                                                  double xmax,
+                                                  unsigned long long *__restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  const int nb2 = nbins + 2;
+  for (int k = threadIdx.x; k < 3 * nb2; k += 256) hist[k] = 0u;
+  __syncthreads();
+  const int64_t N = (int64_t)cp.nx * cp.ny * cp.nz;
+  const double width = 2.0 * xmax / nbins;
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    double u[3];
+    site_velocity<L, S>(cp, buf, s, u);
+    for (int a = 0; a < dims; ++a) {
+      const double x = (u[a] - c.centre[a]) * c.inv_sigma[a];
+      int b;
+      if (!(x >= -xmax)) {
+        b = 0;
+      } else if (x >= xmax) {
+        b = nbins + 1;
+      } else {
+        b = 1 + (int)floor((x + xmax) / width);
+        b = b > nbins ? nbins : b;
+      }
+      atomicAdd(&hist[a * nb2 + b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 3 * nb2; k += 256)
+    if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
+}
+
+// ---------------------------------------------------------------------------
 // batched ensemble: one launch per step over the tiles of every replica
 // ---------------------------------------------------------------------------
 // A tile is spt x kEnsembleBlock consecutive sites (x fastest) of one
@@ -1146,6 +1266,35 @@ hipError_t launch_sk_segments(const double *acc, int64_t M, int nx, int ny, int 
   hipLaunchKernelGGL(k_sk_segments, dim3(nbins), dim3(256), 0, stream, acc, M,
                      shell_geom(nx, ny, nz, nbins), perm, off, out);
   return hipGetLastError();
+}
+
+hipError_t launch_vel_moments(int q, int storage, const ConvParams &cp, const void *buf,
+                              const VelNorm &c, int grid, double *partials, double *out,
+                              hipStream_t stream) {
+  hipError_t e = with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_vel_moments<L, S>), dim3(grid), dim3(256), 0, stream, cp,
+                       static_cast<const S *>(buf), c, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vel_moments_final, dim3(1), dim3(256), 0, stream, partials, grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vel_hist(int q, int storage, const ConvParams &cp, const void *buf,
+                           const VelNorm &c, int grid, int nbins, double xmax,
+                           unsigned long long *counts, hipStream_t stream) {
+  const size_t lds = sizeof(uint32_t) * 3 * (size_t)(nbins + 2);
+  const int dims = q == 9 ? 2 : 3;
+  return with_lattice_storage(q, storage, [&](auto lt, auto stt) {
+    using L = typename decltype(lt)::type;
+    using S = typename decltype(stt)::type;
+    hipLaunchKernelGGL((k_vel_hist<L, S>), dim3(grid), dim3(256), lds, stream, cp,
+                       static_cast<const S *>(buf), c, dims, nbins, xmax, counts);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream) {

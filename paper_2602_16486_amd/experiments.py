@@ -32,9 +32,10 @@ def _emit(rec):
 
 
 def run(q, shape, storage="f32", steps=1000, tau=0.8, kT=1e-4, rho0=1.0, seed=1, lam=None,
-        window=0.5, sk_every=0, nbins=32, chunk=1 << 16):
+        window=0.5, sk_every=0, nbins=32, chunk=1 << 16, pdf_bins=0):
     """Step a rest-state lattice, collecting the per-step <u_a^2> series and
-    optionally the structure factor over the window.  Returns diagnostics."""
+    optionally the structure factor over the window and the velocity PDFs
+    of the final state.  Returns diagnostics."""
     dims = 2 if q == 9 else 3
     n = W.n_sites(shape)
     start = int(steps * (1 - window))
@@ -69,12 +70,26 @@ def run(q, shape, storage="f32", steps=1000, tau=0.8, kT=1e-4, rho0=1.0, seed=1,
                 got += len(st)
                 unread = 0
         sk = lat.sk_shells()[0] if sk_every else None
+        pdf = lat.velocity_pdf(pdf_bins, 5.0) if pdf_bins else None
     series = np.zeros((steps, 12))
     series[:, 8:11] = u2
     out = S.equipartition(series, n, kT, rho0, dims, start=start)
     out["mass_drift"] = float(last[1] - first[1])
     out["momentum_drift"] = float(np.abs(last[2:5] - first[2:5]).max())
     out["seconds"] = time.perf_counter() - t0
+    if pdf is not None:
+        mom, counts = pdf
+        # normalised density of each bin against the unit Gaussian
+        edges = np.linspace(-5.0, 5.0, pdf_bins + 1)
+        width = edges[1] - edges[0]
+        gauss = np.diff([0.5 * math.erfc(-e / math.sqrt(2)) for e in edges])
+        out["pdf"] = {
+            "skewness": mom[:dims, 2].tolist(), "kurtosis": mom[:dims, 3].tolist(),
+            "bins": pdf_bins, "xmax": 5.0,
+            "density": (counts[:dims, 1:-1] / n / width).round(6).tolist(),
+            "max_abs_density_minus_gaussian": float(np.abs(counts[:dims, 1:-1] / n - gauss).max() / width),
+            "outside": counts[:dims, [0, -1]].sum(axis=1).tolist(),
+        }
     if sk is not None:
         w = sk[:, 1]
         su = sk[:, 3:3 + dims].mean(axis=1) / (kT / rho0)
@@ -177,13 +192,14 @@ def test6(scale):
 
 def test7(scale):
     """Test 7: D3Q27 on anisotropic boxes C1-C4, kT = 1/3000, tau = 0.8,
-    T_max = 100 t0 with t0 = N_y / 0.01; Table 3 quantities."""
+    T_max = 100 t0 with t0 = N_y / 0.01; Table 3 quantities and the velocity
+    PDFs of the final state (Fig. 8)."""
     boxes = {"C1": (50, 50, 50), "C2": (25, 50, 100), "C3": (60, 15, 30), "C4": (20, 80, 40)}
     paper = {"C1": [1.42e-6, 1.62e-6, 7.0e-8], "C2": [1.43e-6, 1.62e-6, 9.0e-8],
              "C3": [1.25e-6, 2.26e-6, 2.0e-8], "C4": [8.30e-7, 1.25e-6, 1.8e-7]}
     for name, shape in boxes.items():
         steps = int(100 * shape[1] / 0.01 * scale)
-        r = run(27, shape, steps=steps, tau=0.8, kT=1 / 3000, window=0.99)
+        r = run(27, shape, steps=steps, tau=0.8, kT=1 / 3000, window=0.99, pdf_bins=40)
         _emit({"experiment": "test7", "box": name, "shape": shape, "steps": steps, **r,
                "paper_table3": paper[name]})
 

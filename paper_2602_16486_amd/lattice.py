@@ -118,6 +118,18 @@ class Lattice:
         _lib.check(self._lib.cmf_get_macro(self._h, _lib._d(rho), _lib._d(u)))
         return rho, u
 
+    def velocity_pdf(self, nbins=64, xmax=5.0):
+        """Velocity statistics of the current state (device): returns
+        (moments, counts) with moments shape (3, 4) = mean, variance,
+        skewness, kurtosis per component and counts shape (3, nbins + 2) of
+        x = (u_a - mean_a) / sigma_a (first / last column: below -xmax /
+        at or above xmax)."""
+        mom = np.zeros(12)
+        counts = np.zeros(3 * (nbins + 2), dtype=np.int64)
+        _lib.check(self._lib.cmf_velocity_pdf(self._h, int(nbins), float(xmax), _lib._d(mom),
+                                              counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return mom.reshape(3, 4), counts.reshape(3, nbins + 2)
+
     def gather_sites(self, sites):
         s = np.ascontiguousarray(sites, dtype=np.int64)
         out = np.zeros((s.size, self.q))

@@ -331,3 +331,37 @@ def test_get_macro_matches_populations(q, shape, storage):
     u_ref = (c.T @ g) / rho_ref
     assert np.allclose(r, rho_ref, rtol=1e-14, atol=0)
     assert np.abs(uu - u_ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("q,shape,storage,steps", [(9, (40, 30), "f64", 0), (27, (12, 10, 9), "f64", 0),
+                                                   (27, (12, 10, 9), "f64", 4), (9, (64, 48), "f32", 0)])
+def test_velocity_pdf_matches_oracle(q, shape, storage, steps):
+    """cmf_velocity_pdf (Test 7, Fig. 8) against the oracle's plain
+    definitions on the same state: moments to FP64 (FP32 storage: to the
+    rounding of the stored deviations) and integer counts equal except for
+    values within rounding of a bin edge."""
+    from oracle import pdf as P
+    n = W.n_sites(shape)
+    dims = 2 if q == 9 else 3
+    rho, u = W.random_macro(shape, 31, umax=0.03, dims=dims)
+    f = O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, 32, 5e-4)
+    nbins, xmax = 24, 3.0
+    with Lattice(q, shape, storage=storage, tau=0.7, kT=1e-4, seed=33) as lat:
+        lat.set_populations(f)
+        lat.step(steps)
+        mom, counts = lat.velocity_pdf(nbins, xmax)
+    if steps:
+        O.run(q, shape, f, 1e-4, O.paper_lambda(q, 1 / 0.7), 33, 0, 0, steps)
+    uref = P.velocity(q, f)
+    mref = P.velocity_moments(uref)
+    cref, xs = P.velocity_histogram(uref, dims, nbins, xmax)
+    tol = 1e-12 if storage == "f64" else 1e-5
+    for a in range(dims):
+        assert abs(mom[a, 0] - mref[a, 0]) <= tol * np.sqrt(mref[a, 1])
+        assert np.allclose(mom[a, 1:], mref[a, 1:], rtol=tol * 10, atol=0)
+        edges = np.linspace(-xmax, xmax, nbins + 1)
+        near = int(np.sum(np.min(np.abs(xs[a][:, None] - edges[None, :]), axis=1) < 1e3 * tol))
+        assert np.abs(counts[a] - cref[a]).sum() <= 2 * near, (a, near)
+        assert counts[a].sum() == n
+    if dims == 2:
+        assert not counts[2].any() and not mom[2].any()
