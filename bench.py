@@ -164,20 +164,33 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000):
 
 
 def cpu_baseline():
-    """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 40 steps
-    from rest (same parameters as the GPU workload)."""
-    import numpy as np  # noqa: F401
+    """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 160 steps
+    from rest (same parameters as the GPU workload) with the dense T(u) + LU
+    reconstruction on every thread (the reported value), plus the oracle's
+    second reconstruction form (M^-1 N(-u), 64^3 x 80 steps) and both forms
+    on one core (32^3 x 10 steps)."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    shape, steps = (64, 64, 64), 160
-    n = shape[0] * shape[1] * shape[2]
-    f = O.init_equilibrium(Q, n, rho0=RHO0)
-    t0 = time.perf_counter()
-    O.run(Q, shape, f, KT, O.paper_lambda(Q, 1 / TAU), SEED, 0, 0, steps, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"D3Q27 64^3 x {steps} steps from rest (rho0=1, tau=0.8, kT=1e-4, seed 1), "
-                      f"FP64 dense T(u) + LU, {dt:.1f} s"}
+
+    def timed(shape, steps, method, nthreads):
+        n = shape[0] * shape[1] * shape[2]
+        f = O.init_equilibrium(Q, n, rho0=RHO0)
+        t0 = time.perf_counter()
+        O.run(Q, shape, f, KT, O.paper_lambda(Q, 1 / TAU), SEED, 0, 0, steps, method=method,
+              nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        return n * steps / dt, dt
+
+    rate, dt = timed((64, 64, 64), 160, 0, threads)
+    shift, _ = timed((64, 64, 64), 80, 1, threads)
+    one_lu, _ = timed((32, 32, 32), 10, 0, 1)
+    one_shift, _ = timed((32, 32, 32), 10, 1, 1)
+    return {"value": rate / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"D3Q27 64^3 x 160 steps from rest (rho0=1, tau=0.8, kT=1e-4, seed 1), "
+                      f"FP64 dense T(u) + LU, {dt:.1f} s",
+            "forms_mlups": {"dense_lu": rate / 1e6, "shift_reconstruction": shift / 1e6,
+                            "dense_lu_one_core": one_lu / 1e6,
+                            "shift_reconstruction_one_core": one_shift / 1e6}}
 
 
 def main():
