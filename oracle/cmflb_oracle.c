@@ -33,8 +33,8 @@
  *    breaks orthogonality and contradicts the printed b_15 = 2/27).
  *  - Noise: eta comes from Philox4x32-10 (Salmon et al., SC'11) keyed by the
  *    64-bit seed, counter (site, step, replica, block), mapped to normals by
- *    the Box-Muller transform (details at orc_normals).  The paper only says
- *    "independent standard normal".
+ *    the Box-Muller transform (details at orc_normals).  The paper asks only
+ *    for independent standard normal variables.
  *
  * Parity pins: see the test suite (tests/test_oracle_*.py).  The Philox
  * generator has no published known-answer vector in this repository; it is
