@@ -146,6 +146,76 @@ void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
   }
 }
 
+// Captured runs of kGraphSteps steps: step j passes step offset j and the
+// partial-sum buffer j mod 2 and runs on the caller's stream; its
+// statistics reduction runs on a second stream (default priority) once step
+// j is done, so it overlaps step j + 1; step j + 2 waits for it (it reuses
+// the buffer); the step counter advances once, after the last reduction.
+struct ForkedRun {
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_step[kGraphSteps] = {};
+  hipEvent_t ev_fin[kGraphSteps] = {};
+  bool ready = false;
+};
+
+void forked_release(ForkedRun &F) {
+  for (int j = 0; j < kGraphSteps; ++j) {
+    if (F.ev_step[j]) (void)hipEventDestroy(F.ev_step[j]);
+    if (F.ev_fin[j]) (void)hipEventDestroy(F.ev_fin[j]);
+    F.ev_step[j] = F.ev_fin[j] = nullptr;
+  }
+  if (F.aux) (void)hipStreamDestroy(F.aux);
+  F.aux = nullptr;
+  F.ready = false;
+}
+
+int forked_init(ForkedRun &F) {
+  if (F.ready) return CMF_OK;
+  hipError_t e = hipStreamCreate(&F.aux);
+  for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j) {
+    e = hipEventCreateWithFlags(&F.ev_step[j], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&F.ev_fin[j], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    forked_release(F);
+    return fail(CMF_EHIP, "stream/event creation failed: %s", hipGetErrorString(e));
+  }
+  F.ready = true;
+  return CMF_OK;
+}
+
+// step(j, stream) enqueues step j; fin(j, stream) its statistics reduction
+// (only when `stats`).
+template <class StepFn, class FinFn>
+int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step,
+                   FinFn fin, hipGraphExec_t *out) {
+  if (stats) {
+    int rc = forked_init(F);
+    if (rc != CMF_OK) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j) {
+    if (stats && j >= 2) e = hipStreamWaitEvent(s, F.ev_fin[j - 2], 0);
+    if (e == hipSuccess) e = step(j, s);
+    if (stats) {
+      if (e == hipSuccess) e = hipEventRecord(F.ev_step[j], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(F.aux, F.ev_step[j], 0);
+      if (e == hipSuccess) e = fin(j, F.aux);
+      if (e == hipSuccess) e = hipEventRecord(F.ev_fin[j], F.aux);
+    }
+  }
+  if (stats && e == hipSuccess) e = hipStreamWaitEvent(s, F.ev_fin[kGraphSteps - 1], 0);
+  if (e == hipSuccess) e = launch_bump_step(step_dev, kGraphSteps, s);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  if (e == hipSuccess) e = ec;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(CMF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
 }  // namespace
 
 struct cmf_lattice {
@@ -180,6 +250,7 @@ struct cmf_lattice {
   StepParams<double> pd;
   ConvParams cp;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  ForkedRun forked;
   // structure factor
   int sk_nbins = 0;
   int64_t sk_M = 0, sk_samples = 0;
@@ -297,7 +368,7 @@ int apply_launch(cmf_lattice *L, int block, int grid, const double *amp,
     if (L->partials) (void)hipFree(L->partials);
     L->partials = nullptr;
     L->partials_cap = 0;
-    if (hipMalloc((void **)&L->partials, sizeof(double) * kPartStride * L->nparts) != hipSuccess)
+    if (hipMalloc((void **)&L->partials, 2 * sizeof(double) * kPartStride * L->nparts) != hipSuccess)
       return fail(CMF_ENOMEM, "hipMalloc of the statistics partials failed");
     L->partials_cap = L->nparts;
   }
@@ -309,13 +380,20 @@ const void *step_params(const cmf_lattice *L) {
   return L->storage == kF64 ? (const void *)&L->pd : (const void *)&L->pf;
 }
 
+// partial-sum buffer b (0 or 1) of the lattice
+double *partials_buf(const cmf_lattice *L, int b) {
+  return L->partials + (size_t)b * kPartStride * L->partials_cap;
+}
+
+// One direct step: the fused kernel, then its statistics and the step
+// counter on the same stream.
 int enqueue_one_step(cmf_lattice *L) {
   const void *src = L->buf[L->parity];
   void *dst = L->buf[1 - L->parity];
   HIP_TRY(launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst,
-                      L->step_dev, L->partials, L->grid, L->block, L->stream));
-  HIP_TRY(launch_finalize(L->partials, L->nparts, L->level2, L->series, L->cap,
-                          L->step_dev, L->mass0,
+                      L->step_dev, 0, partials_buf(L, 0), L->grid, L->block, L->stream));
+  HIP_TRY(launch_finalize(partials_buf(L, 0), L->nparts, L->level2, L->series, L->cap,
+                          L->step_dev, 0, 1, L->mass0,
                           !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream));
   L->parity ^= 1;
   return CMF_OK;
@@ -342,25 +420,17 @@ int time_full_steps(cmf_lattice *L, int n, double *ms_out) {
 }
 
 int capture_graph(cmf_lattice *L, int parity) {
-  const int saved = L->parity;
-  L->parity = parity;
-  HIP_TRY(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
-  int rc = CMF_OK;
-  for (int s = 0; s < kGraphSteps && rc == CMF_OK; ++s) rc = enqueue_one_step(L);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(L->stream, &g);
-  L->parity = saved;
-  if (rc != CMF_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
-  }
-  if (e != hipSuccess)
-    return fail(CMF_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&L->graph[parity], g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess)
-    return fail(CMF_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-  return CMF_OK;
+  const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
+  auto step = [&](int j, hipStream_t s) {
+    const int b = parity ^ (j & 1);
+    return launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), L->buf[b],
+                       L->buf[b ^ 1], L->step_dev, j, partials_buf(L, j & 1), L->grid, L->block, s);
+  };
+  auto fin = [&](int j, hipStream_t s) {
+    return launch_finalize(partials_buf(L, j & 1), L->nparts, L->level2, L->series, L->cap,
+                           L->step_dev, j, 0, L->mass0, true, s);
+  };
+  return capture_forked(L->stream, L->forked, stats, L->step_dev, step, fin, &L->graph[parity]);
 }
 
 void release(cmf_lattice *L) {
@@ -378,6 +448,7 @@ void release(cmf_lattice *L) {
   for (void *p : {(void *)L->sk_fields, L->sk_F, (void *)L->sk_acc, (void *)L->sk_out,
                   (void *)L->sk_perm, (void *)L->sk_off})
     if (p) (void)hipFree(p);
+  forked_release(L->forked);
   if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
   delete L;
 }
@@ -643,11 +714,11 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
     hipError_t e = hipEventRecord(ev[2 * s], L->stream);
     if (e == hipSuccess)
       e = launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst, L->step_dev,
-                      L->partials, L->grid, L->block, L->stream);
+                      0, partials_buf(L, 0), L->grid, L->block, L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
     if (e == hipSuccess)
-      e = launch_finalize(L->partials, L->nparts, L->level2, L->series, L->cap, L->step_dev, L->mass0,
-                          !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream);
+      e = launch_finalize(partials_buf(L, 0), L->nparts, L->level2, L->series, L->cap, L->step_dev,
+                          0, 1, L->mass0, !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream);
     if (e != hipSuccess) rc = fail(CMF_EHIP, "profiled step failed: %s", hipGetErrorString(e));
     L->parity ^= 1;
   }
@@ -1100,6 +1171,7 @@ struct cmf_ensemble {
   int64_t *step_dev = nullptr;
   std::vector<int64_t> read_step;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  ForkedRun forked;
 };
 
 namespace {
@@ -1144,39 +1216,40 @@ void ens_release(cmf_ensemble *E) {
   if (E->series) (void)hipFree(E->series);
   if (E->d_mass0) (void)hipFree(E->d_mass0);
   if (E->step_dev) (void)hipFree(E->step_dev);
+  forked_release(E->forked);
   if (E->own_stream && E->stream) (void)hipStreamDestroy(E->stream);
   delete E;
 }
 
+double *ens_partials_buf(const cmf_ensemble *E, int b) {
+  return E->partials + (size_t)b * kPartStride * E->ntiles;
+}
+
+// One direct step (as enqueue_one_step of a lattice).
 int ens_enqueue_step(cmf_ensemble *E) {
   HIP_TRY(launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
-                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
-                               E->partials, E->stream));
-  HIP_TRY(launch_ensemble_finalize(E->storage, E->d_reps, E->n, E->partials, E->series, E->cap,
-                                   E->step_dev, E->d_mass0, !(E->flags & CMF_FLAG_NO_STATS),
-                                   E->stream));
+                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev, 0,
+                               ens_partials_buf(E, 0), E->stream));
+  HIP_TRY(launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, 0), E->series,
+                                   E->cap, E->step_dev, 0, 1, E->d_mass0,
+                                   !(E->flags & CMF_FLAG_NO_STATS), E->stream));
   E->parity ^= 1;
   return CMF_OK;
 }
 
 int ens_capture(cmf_ensemble *E, int parity) {
-  const int saved = E->parity;
-  E->parity = parity;
-  HIP_TRY(hipStreamBeginCapture(E->stream, hipStreamCaptureModeThreadLocal));
-  int rc = CMF_OK;
-  for (int s = 0; s < kGraphSteps && rc == CMF_OK; ++s) rc = ens_enqueue_step(E);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(E->stream, &g);
-  E->parity = saved;
-  if (rc != CMF_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
-  }
-  if (e != hipSuccess) return fail(CMF_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&E->graph[parity], g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return fail(CMF_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-  return CMF_OK;
+  const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
+  auto step = [&](int j, hipStream_t s) {
+    const int b = parity ^ (j & 1);
+    return launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep,
+                                E->ntiles, E->arena[b], E->arena[b ^ 1], E->step_dev, j,
+                                ens_partials_buf(E, j & 1), s);
+  };
+  auto fin = [&](int j, hipStream_t s) {
+    return launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, j & 1),
+                                    E->series, E->cap, E->step_dev, j, 0, E->d_mass0, true, s);
+  };
+  return capture_forked(E->stream, E->forked, stats, E->step_dev, step, fin, &E->graph[parity]);
 }
 
 int ens_check_index(cmf_ensemble *E, int32_t index) {
@@ -1272,7 +1345,7 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
             hipMalloc(&E->arena[1], E->arena_bytes) == hipSuccess &&
             hipMalloc(&E->d_reps, rec * n) == hipSuccess &&
             hipMalloc((void **)&E->d_tile_rep, sizeof(int32_t) * E->ntiles) == hipSuccess &&
-            hipMalloc((void **)&E->partials, sizeof(double) * kPartStride * E->ntiles) == hipSuccess &&
+            hipMalloc((void **)&E->partials, 2 * sizeof(double) * kPartStride * E->ntiles) == hipSuccess &&
             hipMalloc((void **)&E->series, sizeof(double) * kSeriesStride * E->cap * n) == hipSuccess &&
             hipMalloc((void **)&E->d_mass0, sizeof(double) * n) == hipSuccess &&
             hipMalloc((void **)&E->step_dev, sizeof(int64_t)) == hipSuccess;
@@ -1413,13 +1486,13 @@ int cmf_ensemble_profile_steps(cmf_ensemble *E, int64_t nsteps, double *kernel_m
     e = hipEventRecord(ev[2 * s], E->stream);
     if (e == hipSuccess)
       e = launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
-                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev,
-                               E->partials, E->stream);
+                               E->arena[E->parity], E->arena[1 - E->parity], E->step_dev, 0,
+                               ens_partials_buf(E, 0), E->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], E->stream);
     if (e == hipSuccess)
-      e = launch_ensemble_finalize(E->storage, E->d_reps, E->n, E->partials, E->series, E->cap,
-                                   E->step_dev, E->d_mass0, !(E->flags & CMF_FLAG_NO_STATS),
-                                   E->stream);
+      e = launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, 0), E->series,
+                                   E->cap, E->step_dev, 0, 1, E->d_mass0,
+                                   !(E->flags & CMF_FLAG_NO_STATS), E->stream);
     E->parity ^= 1;
   }
   if (e == hipSuccess) e = hipStreamSynchronize(E->stream);

@@ -60,13 +60,18 @@ enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 // launchers (defined in cmflb_kernels.hip); all return hipError_t
 // nt: non-temporal population stores (rows of whole cache lines), else plain
+// The step index of a launch is *step_ptr + step_off: runs of steps
+// captured in a graph pass offsets 0, 1, ... and advance *step_ptr once at
+// their end (launch_bump_step); a direct step passes 0 and its finalize
+// advances *step_ptr by bump = 1.
 hipError_t launch_step(int q, int storage, bool general, bool nt,
                        const void *params, const void *src, void *dst,
-                       const int64_t *step_ptr, double *partials, int grid,
-                       int block, hipStream_t stream);
+                       const int64_t *step_ptr, int step_off, double *partials,
+                       int grid, int block, hipStream_t stream);
 hipError_t launch_finalize(const double *partials, int nparts, double *level2,
-                           double *series, int cap, int64_t *step_ptr,
-                           double mass0, bool stats, hipStream_t stream);
+                           double *series, int cap, int64_t *step_ptr, int step_off,
+                           int bump, double mass0, bool stats, hipStream_t stream);
+hipError_t launch_bump_step(int64_t *step_ptr, int64_t by, hipStream_t stream);
 hipError_t launch_init_eq(int q, int storage, const ConvParams &cp,
                           const double *rho, const double *u, void *buf,
                           hipStream_t stream);
@@ -133,11 +138,11 @@ constexpr int kXcdChunk = 32;
 hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
-                                const int64_t *step_ptr, double *partials,
+                                const int64_t *step_ptr, int step_off, double *partials,
                                 hipStream_t stream);
 hipError_t launch_ensemble_finalize(int storage, const void *reps, int nrep,
                                     const double *partials, double *series,
-                                    int cap, int64_t *step_ptr, double *mass0,
-                                    bool stats, hipStream_t stream);
+                                    int cap, int64_t *step_ptr, int step_off, int bump,
+                                    double *mass0, bool stats, hipStream_t stream);
 
 }  // namespace cmf

@@ -368,9 +368,9 @@ __device__ __forceinline__ TileXY tile_coords(int tile, int nxb, int ny, int bx)
 template <class L, typename S, typename R, bool GENERAL, bool NT>
 __global__ __launch_bounds__(kMaxBlock) void k_step(
     const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
-    const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
+    const int64_t *__restrict__ step_ptr, int step_off, double *__restrict__ partials) {
   constexpr int Q = L::Q;
-  const uint32_t step = (uint32_t)*step_ptr;
+  const uint32_t step = (uint32_t)(*step_ptr + step_off);
   const int BX = blockDim.x;
   const int nx = p.nx, ny = p.ny;
   Acc acc;
@@ -427,11 +427,15 @@ __global__ __launch_bounds__(256) void k_reduce_partials(
   block_sum_rows(partials, lo, hi, level2 + (int64_t)blockIdx.x * kPartStride);
 }
 
+// The statistics row of step *step_ptr + step_off; *step_ptr advances by
+// `bump` (0 inside a captured run of steps, which advances it once at its end).
 __global__ __launch_bounds__(256) void k_finalize(
     const double *__restrict__ rows, int nrows, double *__restrict__ series,
-    int cap, int64_t *__restrict__ step_ptr, double mass0, int stats) {
+    int cap, int64_t *__restrict__ step_ptr, int step_off, int bump, double mass0,
+    int stats) {
   __shared__ double tot[kNAcc];
-  const int64_t step = *step_ptr;
+  const int64_t base = *step_ptr;
+  const int64_t step = base + step_off;
   if (stats) {
     block_sum_rows(rows, 0, nrows, tot);
     __syncthreads();
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(256) void k_finalize(
       for (int k = 1; k < kNAcc; ++k) row[1 + k] = tot[k];
     }
   }
-  if (threadIdx.x == 0) *step_ptr = step + 1;
+  if (threadIdx.x == 0 && bump) *step_ptr = base + bump;
 }
 
 // ---------------------------------------------------------------------------
@@ -889,10 +893,10 @@ template <typename S, typename R, bool GENERAL, bool NT>
 __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
     const S *__restrict__ src, S *__restrict__ dst,
     const ReplicaParams<R> *__restrict__ reps, const int32_t *__restrict__ tile_rep,
-    const int64_t *__restrict__ step_ptr, double *__restrict__ partials) {
+    const int64_t *__restrict__ step_ptr, int step_off, double *__restrict__ partials) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const ReplicaParams<R> &p = reps[tile_rep[tile]];
-  const uint32_t step = (uint32_t)*step_ptr;
+  const uint32_t step = (uint32_t)(*step_ptr + step_off);
   Acc acc;
 #pragma unroll
   for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
@@ -916,11 +920,11 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_ensemble_reduce(
     const ReplicaParams<R> *__restrict__ reps, const double *__restrict__ partials,
     double *__restrict__ series, int cap, const int64_t *__restrict__ step_ptr,
-    const double *__restrict__ mass0) {
+    int step_off, const double *__restrict__ mass0) {
   __shared__ double tot[kNAcc];
   const int r = blockIdx.x;
   const ReplicaParams<R> &p = reps[r];
-  const int64_t step = *step_ptr;
+  const int64_t step = *step_ptr + step_off;
   block_sum_rows(partials, p.tile0, p.tile0 + p.ntiles, tot);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -932,8 +936,8 @@ __global__ __launch_bounds__(256) void k_ensemble_reduce(
   }
 }
 
-__global__ void k_bump_step(int64_t *step_ptr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *step_ptr = *step_ptr + 1;
+__global__ void k_bump_step(int64_t *step_ptr, int64_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step_ptr = *step_ptr + by;
 }
 
 // ---------------------------------------------------------------------------
@@ -945,43 +949,43 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 template <class L, typename S, typename R, bool G, bool NT>
 hipError_t step_one(const void *params, const void *src, void *dst,
-                    const int64_t *step_ptr, double *partials, int grid,
+                    const int64_t *step_ptr, int step_off, double *partials, int grid,
                     int block, hipStream_t stream) {
   const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
   hipLaunchKernelGGL((k_step<L, S, R, G, NT>), dim3(grid), dim3(block), 0, stream,
                      static_cast<const S *>(src), static_cast<S *>(dst), p,
-                     step_ptr, partials);
+                     step_ptr, step_off, partials);
   return hipGetLastError();
 }
 
 template <class L, typename S, typename R>
 hipError_t step_lg(bool general, bool nt, const void *params, const void *src,
-                   void *dst, const int64_t *step_ptr, double *partials,
+                   void *dst, const int64_t *step_ptr, int off, double *partials,
                    int grid, int block, hipStream_t stream) {
   if (general)
-    return nt ? step_one<L, S, R, true, true>(params, src, dst, step_ptr, partials, grid, block, stream)
-              : step_one<L, S, R, true, false>(params, src, dst, step_ptr, partials, grid, block, stream);
-  return nt ? step_one<L, S, R, false, true>(params, src, dst, step_ptr, partials, grid, block, stream)
-            : step_one<L, S, R, false, false>(params, src, dst, step_ptr, partials, grid, block, stream);
+    return nt ? step_one<L, S, R, true, true>(params, src, dst, step_ptr, off, partials, grid, block, stream)
+              : step_one<L, S, R, true, false>(params, src, dst, step_ptr, off, partials, grid, block, stream);
+  return nt ? step_one<L, S, R, false, true>(params, src, dst, step_ptr, off, partials, grid, block, stream)
+            : step_one<L, S, R, false, false>(params, src, dst, step_ptr, off, partials, grid, block, stream);
 }
 
 template <class L>
 hipError_t step_l(int storage, bool general, bool nt, const void *params,
-                  const void *src, void *dst, const int64_t *step_ptr,
+                  const void *src, void *dst, const int64_t *step_ptr, int off,
                   double *partials, int grid, int block, hipStream_t stream) {
   switch (storage) {
     case kF64:
-      return step_lg<L, double, double>(general, nt, params, src, dst, step_ptr,
+      return step_lg<L, double, double>(general, nt, params, src, dst, step_ptr, off,
                                         partials, grid, block, stream);
     case kF32:
-      return step_lg<L, float, float>(general, nt, params, src, dst, step_ptr,
+      return step_lg<L, float, float>(general, nt, params, src, dst, step_ptr, off,
                                       partials, grid, block, stream);
     case kF16:
-      return step_lg<L, __half, float>(general, nt, params, src, dst, step_ptr,
+      return step_lg<L, __half, float>(general, nt, params, src, dst, step_ptr, off,
                                        partials, grid, block, stream);
     case kBF16:
       return step_lg<L, __hip_bfloat16, float>(general, nt, params, src, dst,
-                                               step_ptr, partials, grid, block,
+                                               step_ptr, off, partials, grid, block,
                                                stream);
   }
   return hipErrorInvalidValue;
@@ -991,20 +995,20 @@ hipError_t step_l(int storage, bool general, bool nt, const void *params,
 
 hipError_t launch_step(int q, int storage, bool general, bool nt,
                        const void *params, const void *src, void *dst,
-                       const int64_t *step_ptr, double *partials, int grid,
-                       int block, hipStream_t stream) {
+                       const int64_t *step_ptr, int step_off, double *partials,
+                       int grid, int block, hipStream_t stream) {
   if (q == 9)
-    return step_l<D2Q9>(storage, general, nt, params, src, dst, step_ptr,
+    return step_l<D2Q9>(storage, general, nt, params, src, dst, step_ptr, step_off,
                         partials, grid, block, stream);
   if (q == 27)
-    return step_l<D3Q27>(storage, general, nt, params, src, dst, step_ptr,
+    return step_l<D3Q27>(storage, general, nt, params, src, dst, step_ptr, step_off,
                          partials, grid, block, stream);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(const double *partials, int nparts, double *level2,
-                           double *series, int cap, int64_t *step_ptr,
-                           double mass0, bool stats, hipStream_t stream) {
+                           double *series, int cap, int64_t *step_ptr, int step_off,
+                           int bump, double mass0, bool stats, hipStream_t stream) {
   const double *rows = partials;
   int nrows = nparts;
   if (stats && nparts > kLevel2Threshold) {
@@ -1020,7 +1024,7 @@ hipError_t launch_finalize(const double *partials, int nparts, double *level2,
     nrows = nb;
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, rows, nrows,
-                     series, cap, step_ptr, mass0, stats ? 1 : 0);
+                     series, cap, step_ptr, step_off, bump, mass0, stats ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1170,7 +1174,7 @@ hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
 hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
-                                const int64_t *step_ptr, double *partials,
+                                const int64_t *step_ptr, int step_off, double *partials,
                                 hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   auto go = [&](auto stt, auto rt, auto gt, auto ntt) {
@@ -1181,7 +1185,7 @@ hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *
     hipLaunchKernelGGL((k_ensemble_step<S, R, G, NT>), dim3(ntiles), dim3(kEnsembleBlock), 0,
                        stream, static_cast<const S *>(src), static_cast<S *>(dst),
                        static_cast<const ReplicaParams<R> *>(reps), tile_rep, step_ptr,
-                       partials);
+                       step_off, partials);
     return hipGetLastError();
   };
   auto by_nt = [&](auto stt, auto rt, auto gt) {
@@ -1201,23 +1205,25 @@ hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *
 
 hipError_t launch_ensemble_finalize(int storage, const void *reps, int nrep,
                                     const double *partials, double *series,
-                                    int cap, int64_t *step_ptr, double *mass0,
-                                    bool stats, hipStream_t stream) {
-  if (!stats) {
-    hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr);
-    return hipGetLastError();
+                                    int cap, int64_t *step_ptr, int step_off, int bump,
+                                    double *mass0, bool stats, hipStream_t stream) {
+  if (stats) {
+    if (storage == kF64)
+      hipLaunchKernelGGL(k_ensemble_reduce<double>, dim3(nrep), dim3(256), 0, stream,
+                         static_cast<const ReplicaParams<double> *>(reps), partials,
+                         series, cap, step_ptr, step_off, mass0);
+    else
+      hipLaunchKernelGGL(k_ensemble_reduce<float>, dim3(nrep), dim3(256), 0, stream,
+                         static_cast<const ReplicaParams<float> *>(reps), partials,
+                         series, cap, step_ptr, step_off, mass0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  if (storage == kF64)
-    hipLaunchKernelGGL(k_ensemble_reduce<double>, dim3(nrep), dim3(256), 0, stream,
-                       static_cast<const ReplicaParams<double> *>(reps), partials,
-                       series, cap, step_ptr, mass0);
-  else
-    hipLaunchKernelGGL(k_ensemble_reduce<float>, dim3(nrep), dim3(256), 0, stream,
-                       static_cast<const ReplicaParams<float> *>(reps), partials,
-                       series, cap, step_ptr, mass0);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr);
+  return bump ? launch_bump_step(step_ptr, bump, stream) : hipSuccess;
+}
+
+hipError_t launch_bump_step(int64_t *step_ptr, int64_t by, hipStream_t stream) {
+  hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, stream, step_ptr, by);
   return hipGetLastError();
 }
 
