@@ -122,7 +122,27 @@ int cmf_device_count(void);
  * [0, 2], N >= 2^31, nx >= 2^28), CMF_ENOMEM, CMF_EHIP. */
 int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
 
-/* Release all device memory of the lattice (synchronises its stream). */
+/* As cmf_create, but the two population buffers live in caller-owned device
+ * memory (for instance a torch tensor): dev_ptr, 256-byte aligned, on the
+ * current device, holding at least cmf_external_bytes(desc) bytes; buffer 0
+ * starts at dev_ptr, buffer 1 half-way.  Their contents are the library's
+ * internal storage (deviations f - w rho0, scaled for 16-bit storage, in a
+ * row-interleaved order), not the canonical populations: read those with
+ * cmf_get_populations.  The lattice writes the rest state into the buffers,
+ * never frees them, and the caller
+ * keeps it alive until cmf_destroy.  Statistics scratch is still allocated by
+ * the library.  Errors: those of cmf_create, CMF_EINVAL when dev_ptr is NULL,
+ * misaligned, too small or not device memory of the current device. */
+int cmf_create_external(const cmf_desc *desc, void *dev_ptr, size_t bytes, void *hip_stream,
+                        cmf_lattice **out);
+
+/* Bytes cmf_create_external needs for `desc` (two population buffers, each
+ * q x N elements of the storage type rounded up to 256 bytes); 0 when the
+ * descriptor is invalid. */
+size_t cmf_external_bytes(const cmf_desc *desc);
+
+/* Release all device memory the lattice allocated (synchronises its
+ * stream); caller-owned buffers of cmf_create_external are left alone. */
 int cmf_destroy(cmf_lattice *lat);
 
 /* Set the state to the equilibrium f_eq(rho, u) of eq. feq (maximal Hermite

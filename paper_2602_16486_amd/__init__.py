@@ -9,4 +9,4 @@ loudly when it has not been built.
 """
 from ._lib import CmfError, STAT_COLUMNS, load, noise_sample, philox_words, version  # noqa: F401
 from .ensemble import Ensemble  # noqa: F401
-from .lattice import Lattice, rate_vector  # noqa: F401
+from .lattice import Lattice, external_bytes, rate_vector  # noqa: F401

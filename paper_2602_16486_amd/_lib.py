@@ -75,7 +75,12 @@ def library_path():
 
 
 def load():
-    """Load the built HIP library; raises if it has not been built."""
+    """Load the built HIP library; raises if it has not been built.
+
+    When PyTorch shares the process (device buffers, streams), import torch
+    before the first call: the torch wheel carries its own HIP runtime, and
+    the library must bind to that one (a HIP runtime loaded after another one
+    sees no device)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -104,6 +109,10 @@ def load():
     lib.cmf_stats.argtypes = [vp, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_sample_macro.argtypes = [vp, vp, vp]
     lib.cmf_get_macro.argtypes = [vp, _dp, _dp]
+    lib.cmf_create_external.argtypes = [ctypes.POINTER(Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.cmf_create_external.restype = ctypes.c_int
+    lib.cmf_external_bytes.argtypes = [ctypes.POINTER(Desc)]
+    lib.cmf_external_bytes.restype = ctypes.c_size_t
     lib.cmf_velocity_pdf.argtypes = [vp, i32, ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_noise_sample.argtypes = [i32, u64, u32, u32, i64, i64, i32, _dp]
     lib.cmf_philox_words.argtypes = [ctypes.POINTER(ctypes.c_uint32), i64, u32, u32,

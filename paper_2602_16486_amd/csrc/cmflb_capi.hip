@@ -225,6 +225,7 @@ struct cmf_lattice {
   bool general = false;
   bool nt_stores = true;  // population rows are whole cache lines
   bool own_stream = false;
+  bool own_bufs = true;  // false: the population buffers belong to the caller
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t N = 0;
@@ -438,7 +439,7 @@ void release(cmf_lattice *L) {
   if (L->stream) (void)hipStreamSynchronize(L->stream);
   for (int k = 0; k < 2; ++k) {
     if (L->graph[k]) (void)hipGraphExecDestroy(L->graph[k]);
-    if (L->buf[k]) (void)hipFree(L->buf[k]);
+    if (L->buf[k] && L->own_bufs) (void)hipFree(L->buf[k]);
   }
   if (L->partials) (void)hipFree(L->partials);
   if (L->level2) (void)hipFree(L->level2);
@@ -488,11 +489,33 @@ int cmf_device_count(void) {
   return n;
 }
 
-int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
+namespace {
+
+// bytes of one population buffer (q x N elements, rounded up to 256)
+size_t buffer_bytes(const cmf_desc *d) {
+  return ((size_t)d->q * d->nx * d->ny * d->nz * storage_bytes(d->storage) + 255) / 256 * 256;
+}
+
+int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext_bytes,
+                   cmf_lattice **out) {
   if (!out) return fail(CMF_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate(desc);
   if (rc != CMF_OK) return rc;
+  if (ext) {
+    const size_t need = 2 * buffer_bytes(desc);
+    if (reinterpret_cast<uintptr_t>(ext) % 256 != 0)
+      return fail(CMF_EINVAL, "external buffer is not 256-byte aligned");
+    if (ext_bytes < need)
+      return fail(CMF_EINVAL, "external buffer holds %zu bytes, the lattice needs %zu", ext_bytes, need);
+    hipPointerAttribute_t attr;
+    int dev = 0;
+    if (hipPointerGetAttributes(&attr, ext) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
+      (void)hipGetLastError();
+      return fail(CMF_EINVAL, "external buffer is not device memory of the current device");
+    }
+  }
   cmf_lattice *L = new cmf_lattice();
   L->desc = *desc;
   L->desc.lambda = nullptr;
@@ -547,11 +570,17 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
     }
     L->own_stream = true;
   }
-  const size_t bytes = ((size_t)q * L->N * storage_bytes(L->storage) + 255) / 256 * 256;
-  for (int k = 0; k < 2; ++k) {
-    if (hipMalloc(&L->buf[k], bytes) != hipSuccess) {
-      release(L);
-      return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  const size_t bytes = buffer_bytes(desc);
+  if (ext) {
+    L->own_bufs = false;
+    L->buf[0] = ext;
+    L->buf[1] = static_cast<char *>(ext) + bytes;
+  } else {
+    for (int k = 0; k < 2; ++k) {
+      if (hipMalloc(&L->buf[k], bytes) != hipSuccess) {
+        release(L);
+        return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+      }
     }
   }
   if (hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
@@ -587,6 +616,23 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
     return rc;
   }
   return CMF_OK;
+}
+
+}  // namespace
+
+int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out) {
+  return create_lattice(desc, hip_stream, nullptr, 0, out);
+}
+
+int cmf_create_external(const cmf_desc *desc, void *dev_ptr, size_t bytes, void *hip_stream,
+                        cmf_lattice **out) {
+  if (!dev_ptr) return fail(CMF_EINVAL, "dev_ptr is NULL");
+  return create_lattice(desc, hip_stream, dev_ptr, bytes, out);
+}
+
+size_t cmf_external_bytes(const cmf_desc *desc) {
+  if (validate(desc) != CMF_OK) return 0;
+  return 2 * buffer_bytes(desc);
 }
 
 int cmf_destroy(cmf_lattice *L) {

@@ -37,17 +37,30 @@ def rate_vector(q, tau, kind="paper"):
     return lam
 
 
+def external_bytes(q, shape, storage="f32"):
+    """Device bytes a lattice needs for its two population buffers when they
+    are provided by the caller (``Lattice(..., external=(ptr, nbytes))``)."""
+    lib = _lib.load()
+    d, _ = _lib.make_desc(q, shape, storage=storage)
+    n = lib.cmf_external_bytes(ctypes.byref(d))
+    if n == 0:
+        raise ValueError("invalid lattice description")
+    return int(n)
+
+
 class Lattice:
     """A periodic D2Q9 or D3Q27 box stepped by the fused CM-FLBM kernel.
 
     ``shape`` is (nx, ny) or (nx, ny, nz); ``storage`` one of f64, f32, f16,
     bf16; ``lam`` optional per-mode relaxation rates (default: the paper's);
     ``stream`` an optional hipStream_t handle (int), e.g.
-    ``torch.cuda.current_stream().cuda_stream``.
+    ``torch.cuda.current_stream().cuda_stream``; ``external`` an optional
+    (device pointer, bytes) pair of caller-owned memory for the population
+    buffers (see :func:`external_bytes`), e.g. from a torch tensor.
     """
 
     def __init__(self, q, shape, storage="f32", rho0=1.0, tau=0.8, kT=0.0, lam=None, seed=1,
-                 replica=0, flags=0, stream=None, series_capacity=0):
+                 replica=0, flags=0, stream=None, series_capacity=0, external=None):
         self._lib = _lib.load()
         nx, ny, nz = (tuple(int(s) for s in shape) + (1, 1))[:3]
         self.q = int(q)
@@ -70,8 +83,14 @@ class Lattice:
         d.series_capacity = int(series_capacity)
         self.rho0, self.tau, self.kT = float(rho0), float(tau), float(kT)
         handle = ctypes.c_void_p()
-        _lib.check(self._lib.cmf_create(ctypes.byref(d), ctypes.c_void_p(stream or 0),
-                                        ctypes.byref(handle)))
+        if external is None:
+            _lib.check(self._lib.cmf_create(ctypes.byref(d), ctypes.c_void_p(stream or 0),
+                                            ctypes.byref(handle)))
+        else:
+            ptr, nbytes = external
+            _lib.check(self._lib.cmf_create_external(ctypes.byref(d), ctypes.c_void_p(int(ptr)),
+                                                     int(nbytes), ctypes.c_void_p(stream or 0),
+                                                     ctypes.byref(handle)))
         self._h = handle
 
     # -- lifetime -----------------------------------------------------------

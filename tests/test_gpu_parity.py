@@ -365,3 +365,35 @@ def test_velocity_pdf_matches_oracle(q, shape, storage, steps):
         assert counts[a].sum() == n
     if dims == 2:
         assert not counts[2].any() and not mom[2].any()
+
+
+def test_external_buffers_from_torch():
+    """cmf_create_external: population buffers in a torch tensor give the
+    same populations and statistics as library-owned buffers; bad buffers
+    are rejected."""
+    import torch
+    from paper_2602_16486_amd import external_bytes
+    q, shape = 27, (24, 20, 18)
+    n = W.n_sites(shape)
+    rho, u = W.random_macro(shape, 41, umax=0.03)
+    f = O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, 42, 5e-4)
+    nbytes = external_bytes(q, shape, "f32")
+    assert nbytes == 2 * ((q * n * 4 + 255) // 256 * 256)
+    t = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (t.data_ptr() + 255) // 256 * 256
+    torch.cuda.synchronize()
+    out = []
+    for ext in (None, (base, nbytes)):
+        with Lattice(q, shape, storage="f32", tau=0.7, kT=1e-4, seed=43, external=ext) as lat:
+            lat.set_populations(f)
+            lat.step(37)
+            out.append((lat.get_populations(), lat.stats()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert t.count_nonzero().item() > 0  # the lattice wrote into the tensor
+    for bad in ((base + 64, nbytes), (base, nbytes - 256)):
+        with pytest.raises(_lib.CmfError):
+            Lattice(q, shape, storage="f32", external=bad)
+    host = np.zeros(nbytes, dtype=np.uint8)
+    with pytest.raises(_lib.CmfError):
+        Lattice(q, shape, storage="f32", external=(host.ctypes.data, nbytes))
