@@ -31,6 +31,13 @@
  *    twice, each with coefficient 1/(n_x! n_y! n_z! c_s^(2n)).
  *  - D3Q27 basis row 15 is (c_y^2 - c_s^2) c_z (the printed c_s^2 c_y term
  *    breaks orthogonality and contradicts the printed b_15 = 2/27).
+ *  - D3Q19 (Sec. 2.4): the velocities are taken in the D3Q27 order of
+ *    Sec. 2.3 with the eight corners left out (the paper lists the set, not
+ *    an order).  Its printed equilibrium does not conserve mass; the paper
+ *    also states that the equilibrium's central moments are (rho, 0, ..., 0),
+ *    which fixes it uniquely: k_eq = rho e_0 is used in the collision and
+ *    f_eq = T(u)^-1 rho e_0 (LU solve) as the equilibrium.  The second
+ *    reconstruction path does not apply on D3Q19 (N(u)^-1 != N(-u) there).
  *  - Noise: eta comes from Philox4x32-10 (Salmon et al., SC'11) keyed by the
  *    64-bit seed, counter (site, step, replica, block), mapped to normals by
  *    the Box-Muller transform (details at orc_normals).  The paper asks only
@@ -78,7 +85,7 @@ static double d3q27_weight(int i) {
   return 1.0 / 216.0;
 }
 
-static int lattice_ok(int q) { return q == 9 || q == 27; }
+static int lattice_ok(int q) { return q == 9 || q == 19 || q == 27; }
 
 static void velocity(int q, int i, double c[3]) {
   if (q == 9) {
@@ -92,8 +99,15 @@ static void velocity(int q, int i, double c[3]) {
   }
 }
 
+/* D3Q19 weights (Sec. 2.4): 1/3, 1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2). */
+static double d3q19_weight(int i) {
+  if (i == 0) return 1.0 / 3.0;
+  return i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0;
+}
+
 static double weight(int q, int i) {
-  return q == 9 ? d2q9_w[i] : d3q27_weight(i);
+  if (q == 9) return d2q9_w[i];
+  return q == 19 ? d3q19_weight(i) : d3q27_weight(i);
 }
 
 /* ---- moment bases ------------------------------------------------------- */
@@ -170,10 +184,38 @@ static double d3q27_row(int v, double x, double y, double z) {
   return 0.0;
 }
 
+/* Row v of the D3Q19 basis (Sec. 2.4), with c^2 = x^2 + y^2 + z^2. */
+static double d3q19_row(int v, double x, double y, double z) {
+  const double c2 = x * x + y * y + z * z;
+  switch (v) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return x * z;
+    case 10: return x * (3.0 * c2 - 5.0);
+    case 11: return y * (3.0 * c2 - 5.0);
+    case 12: return z * (3.0 * c2 - 5.0);
+    case 13: return x * (y * y - z * z);
+    case 14: return y * (z * z - x * x);
+    case 15: return z * (x * x - y * y);
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+    case 18: return (2.0 * c2 - 3.0) * (y * y - z * z);
+  }
+  return 0.0;
+}
+
 static double basis_row(int q, int basis, int v, const double c[3]) {
   if (q == 9)
     return basis == 1 ? d2q9_nonorth_row(v, c[0], c[1])
                       : d2q9_orth_row(v, c[0], c[1]);
+  if (q == 19) return d3q19_row(v, c[0], c[1], c[2]);
   return d3q27_row(v, c[0], c[1], c[2]);
 }
 
@@ -272,12 +314,23 @@ static void ctx_init(ctx_t *x, int q, int basis) {
   x->nm = nm;
 }
 
+static int lu_solve(int q, const double *A_in, const double *b_in, double *x);
+
 /* f_eq_i = w_i rho sum_m H_m(c_i) u^m / (m_x! m_y! m_z! c_s^(2|m|)) over
  * multi-indices m with every m_a <= 2 (the terms kept by the paper's D2Q9
  * and D3Q27 equilibria; a full tensor contraction groups each multi-index
- * with multiplicity n!/(m_x! m_y! m_z!)). */
+ * with multiplicity n!/(m_x! m_y! m_z!)).  D3Q19: the state whose central
+ * moments are (rho, 0, ..., 0), f_eq = T(u)^-1 rho e_0. */
 static void equilibrium(const ctx_t *x, double rho, const double u[3],
                         double *feq) {
+  if (x->q == 19) {
+    double T[ORC_QMAX * ORC_QMAX], k[ORC_QMAX] = {0};
+    build_T(19, 0, u, T);
+    k[0] = rho;
+    if (lu_solve(19, T, k, feq) != 0)
+      for (int i = 0; i < 19; ++i) feq[i] = NAN;
+    return;
+  }
   double um[ORC_QMAX];
   for (int m = 0; m < x->nm; ++m) {
     double p = 1.0;
@@ -464,9 +517,14 @@ static int collide_site(const ctx_t *x, int method, double kT,
   /* step 3: k = T(u) f */
   build_T(q, x->basis, u, T);
   matvec(q, T, f, k);
-  /* k_eq = T(u) f_eq(rho, u) */
-  equilibrium(x, rho, u, feq);
-  matvec(q, T, feq, keq);
+  /* k_eq = T(u) f_eq(rho, u); D3Q19: k_eq = (rho, 0, ..., 0) as stated */
+  if (q == 19) {
+    for (int v = 0; v < q; ++v) keq[v] = 0.0;
+    keq[0] = rho;
+  } else {
+    equilibrium(x, rho, u, feq);
+    matvec(q, T, feq, keq);
+  }
   /* step 4: eq. cm_collision, phi from eq. phi_general with the local rho */
   const int first = first_noisy_mode(q);
   for (int v = 0; v < q; ++v) {
@@ -493,6 +551,9 @@ static int collide_site(const ctx_t *x, int method, double kT,
 static int args_ok(int q, int basis) {
   return lattice_ok(q) && (basis == 0 || (basis == 1 && q == 9));
 }
+
+/* the second reconstruction path needs N(u)^-1 = N(-u) (not on D3Q19) */
+static int method_ok(int q, int method) { return method == 0 || (method == 1 && q != 19); }
 
 int orc_lattice(int q, int32_t *c, double *w) {
   if (!lattice_ok(q)) return -1;
@@ -533,7 +594,7 @@ int orc_equilibrium(int q, double rho, const double *u, double *feq) {
 
 /* Relaxation rates of the paper: D2Q9 Lambda = diag[1,1,1,1,w,w,1,1,1]
  * (Sec. 2.2); D3Q27 Lambda_0-6 = Lambda_10-26 = 1, Lambda_7-9 = w
- * (Sec. 2.3), with w = 1/tau. */
+ * (Sec. 2.3); D3Q19 Lambda_7-9 = w, the rest 1 (Sec. 2.4); w = 1/tau. */
 int orc_paper_lambda(int q, double omega, double *lambda) {
   if (!lattice_ok(q)) return -1;
   for (int v = 0; v < q; ++v) lambda[v] = 1.0;
@@ -561,7 +622,7 @@ int orc_collide_site(int q, int basis, int method, double kT,
                      const double *lambda, const double *f, const double *eta,
                      double *out_macro, double *kpre, double *kstar,
                      double *fstar) {
-  if (!args_ok(q, basis)) return -1;
+  if (!args_ok(q, basis) || !method_ok(q, method)) return -1;
   ctx_t x;
   ctx_init(&x, q, basis);
   macro_t m;
@@ -590,7 +651,7 @@ int orc_collide_site(int q, int basis, int method, double kT,
 int orc_run(int q, int basis, int method, int nx, int ny, int nz, double kT,
             const double *lambda, uint64_t seed, uint32_t replica, double *f,
             int64_t step0, int64_t nsteps, double *stats, int nthreads) {
-  if (!args_ok(q, basis) || nx < 1 || ny < 1 || nz < 1) return -1;
+  if (!args_ok(q, basis) || !method_ok(q, method) || nx < 1 || ny < 1 || nz < 1) return -1;
   if (q == 9 && nz != 1) return -1;
   ctx_t x;
   ctx_init(&x, q, basis);

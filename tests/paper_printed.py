@@ -1,5 +1,5 @@
-"""The paper's printed D2Q9 formulas, typed as printed, used as pins for the
-oracle (De Rosis & Zhou, arXiv 2602.16486).
+"""The paper's printed D2Q9 and D3Q19 formulas, typed as printed, used as pins
+for the oracle (De Rosis & Zhou, arXiv 2602.16486).
 
 Each function follows one block of printed equations:
   * ``d2q9_printed_collision`` -- Sec. 2.2: eq. (macro), eq. (pre_coll_rms),
@@ -11,6 +11,8 @@ Each function follows one block of printed equations:
     the absence of noise.
   * ``d2q9_printed_nonorth_deterministic`` -- Sec. 3, Test 2: post-collision
     central moments, raw moments and populations of the non-orthogonal basis.
+  * ``d3q19_printed_feq`` -- Sec. 2.4: the fourth-order D3Q19 equilibrium
+    (rest, axis and face-diagonal expressions).
 """
 import math
 
@@ -109,3 +111,31 @@ def d2q9_printed_nonorth_deterministic(f, omega):
     fs[7] = (r[5] - r[6] - r[7] + r[8]) / 4
     fs[8] = (-r[5] - r[6] + r[7] + r[8]) / 4
     return {"rstar": r, "fstar": fs}
+
+
+def d3q19_printed_feq(rho, u, c):
+    """Sec. 2.4 equilibrium for the velocities c ((19, 3) integers), as
+    printed: rest, axis (one non-zero component alpha) and face-diagonal
+    (components alpha, beta non-zero, gamma zero) populations."""
+    u = np.asarray(u, dtype=float)
+    u2 = float(u @ u)
+    f = np.zeros(len(c))
+    for i, ci in enumerate(c):
+        nz = [a for a in range(3) if ci[a] != 0]
+        if not nz:
+            f[i] = rho * (1.0 / 3.0 + u2 / 6.0 + 0.5 * u2 * u2)
+        elif len(nz) == 1:
+            a = nz[0]
+            cu = ci[a] * u[a]
+            f[i] = rho * (1.0 / 18.0 + cu / 6.0 - u2 / 3.0 - 0.5 * cu * u2 + 0.5 * u2 * u2)
+        else:
+            a, b = nz
+            g = 3 - a - b
+            ca, cb = ci[a], ci[b]
+            ua, ub, ug = u[a], u[b], u[g]
+            f[i] = rho * (1.0 / 36.0 + (ca * ua + cb * ub) / 12.0 + 5.0 / 24.0 * (ua ** 2 + ub ** 2)
+                          - ug ** 2 / 8.0 + ca * cb * ua * ub / 4.0
+                          + (ca * ua ** 3 + cb * ub ** 3) / 8.0
+                          + (ca * ua * ub ** 2 + cb * ub * ua ** 2) / 4.0
+                          - (ua ** 4 + ub ** 4) / 8.0 + ua ** 2 * ub ** 2 / 4.0 + 3.0 / 8.0 * ug ** 4)
+    return f
