@@ -61,11 +61,37 @@ void lattice_weights(double *w) {
            (L::D == 3 ? axis_weight(L::cz[i]) : 1.0);
 }
 
+// D3Q19 weights (Sec. 2.4): 1/3 at rest, 1/18 on the axes, 1/36 on the
+// face diagonals
+void d3q19_weights(double *w) {
+  for (int i = 0; i < 19; ++i) w[i] = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// the D3Q19 basis polynomials of Sec. 2.4 at c
+void d3q19_basis(double x, double y, double z, double *P) {
+  const double c2 = x * x + y * y + z * z;
+  const double row[19] = {1.0, x, y, z, c2 - 1.0, 3.0 * x * x - c2, y * y - z * z, x * y, y * z,
+                          x * z, x * (3.0 * c2 - 5.0), y * (3.0 * c2 - 5.0), z * (3.0 * c2 - 5.0),
+                          x * (y * y - z * z), y * (z * z - x * x), z * (x * x - y * y),
+                          3.0 * c2 * c2 - 6.0 * c2 + 1.0, (2.0 * c2 - 3.0) * (3.0 * x * x - c2),
+                          (2.0 * c2 - 3.0) * (y * y - z * z)};
+  for (int v = 0; v < 19; ++v) P[v] = row[v];
+}
+
 // b_v of the paper's orthogonal bases (Sec. 2.2 and 2.3): products of the
 // one-axis norms; D2Q9 rows 3 and 4 are sums/differences of two orthogonal
-// products and have norm 2/9 + 2/9.
+// products and have norm 2/9 + 2/9.  D3Q19 (Sec. 2.4): sum_i w_i P_v(c_i)^2.
 void mode_norms(int q, double *b) {
-  if (q == 27) {
+  if (q == 19) {
+    double w[19];
+    d3q19_weights(w);
+    for (int v = 0; v < 19; ++v) b[v] = 0.0;
+    for (int i = 0; i < 19; ++i) {
+      double P[19];
+      d3q19_basis(D3Q19::cx[i], D3Q19::cy[i], D3Q19::cz[i], P);
+      for (int v = 0; v < 19; ++v) b[v] += w[i] * P[v] * P[v];
+    }
+  } else if (q == 27) {
     for (int v = 0; v < 27; ++v) {
       const int pos = D3Q27::mode_pos[v];
       b[v] = kAxisNorm[pos % 3] * kAxisNorm[(pos / 3) % 3] * kAxisNorm[pos / 9];
@@ -129,7 +155,12 @@ void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
     if (!is_omega_mode(q, v) && mc.lambda[v] != 1.0) mc.general = true;
   if (env_int("CMF_FORCE_GENERAL", 0)) mc.general = true;
   double b[27];
-  if (q == 9) lattice_weights<D2Q9>(mc.w); else lattice_weights<D3Q27>(mc.w);
+  if (q == 9)
+    lattice_weights<D2Q9>(mc.w);
+  else if (q == 19)
+    d3q19_weights(mc.w);
+  else
+    lattice_weights<D3Q27>(mc.w);
   mode_norms(q, b);
   for (int v = 0; v < q; ++v) {
     const double lv = mc.lambda[v];
@@ -456,7 +487,8 @@ void release(cmf_lattice *L) {
 
 int validate(const cmf_desc *d) {
   if (!d) return fail(CMF_EINVAL, "desc is NULL");
-  if (d->q != 9 && d->q != 27) return fail(CMF_EINVAL, "q must be 9 or 27, got %d", d->q);
+  if (d->q != 9 && d->q != 19 && d->q != 27)
+    return fail(CMF_EINVAL, "q must be 9, 19 or 27, got %d", d->q);
   if (d->nx < 1 || d->ny < 1 || d->nz < 1)
     return fail(CMF_EINVAL, "box edges must be >= 1 (%d, %d, %d)", d->nx, d->ny, d->nz);
   if (d->q == 9 && d->nz != 1) return fail(CMF_EINVAL, "D2Q9 needs nz = 1, got %d", d->nz);
@@ -1116,7 +1148,7 @@ int cmf_velocity_pdf(cmf_lattice *L, int32_t nbins, double xmax, double *moments
 
 int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step, int64_t site0,
                      int64_t n, int32_t fp64, double *out) {
-  if (q != 9 && q != 27) return fail(CMF_EINVAL, "q must be 9 or 27");
+  if (q != 9 && q != 19 && q != 27) return fail(CMF_EINVAL, "q must be 9, 19 or 27");
   if (n < 0 || site0 < 0 || site0 + n > ((int64_t)1 << 32)) return fail(CMF_EINVAL, "bad site range");
   if (n == 0) return CMF_OK;
   if (!out) return fail(CMF_EINVAL, "out is NULL");
@@ -1358,18 +1390,18 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     }
     E->total_sites += rp.N;
   }
-  // sites per thread (CMF_ENSEMBLE_SPT9 / CMF_ENSEMBLE_SPT27 override the
-  // defaults, 1..16)
+  // sites per thread (CMF_ENSEMBLE_SPT9 / CMF_ENSEMBLE_SPT27, the latter for
+  // both 3-D lattices, override the defaults, 1..16)
   const int spt9 = env_int("CMF_ENSEMBLE_SPT9", kEnsembleSpt9, 1, 16);
   const int spt27 = env_int("CMF_ENSEMBLE_SPT27", kEnsembleSpt27, 1, 16);
-  // tiles: D3Q27 replicas first, then D2Q9, each in creation order
+  // tiles: 3-D replicas first, then D2Q9, each in creation order
   std::vector<int32_t> tile_rep;
   for (int pass = 0; pass < 2; ++pass)
     for (int r = 0; r < n; ++r) {
-      if ((pass == 0) != (descs[r].q == 27)) continue;
+      if ((pass == 0) != (descs[r].q != 9)) continue;
       cmf_ensemble::Rep &rp = E->reps[r];
       rp.tile0 = (int)tile_rep.size();
-      rp.spt = descs[r].q == 27 ? spt27 : spt9;
+      rp.spt = descs[r].q == 9 ? spt9 : spt27;
       const int64_t tsites = (int64_t)rp.spt * kEnsembleBlock;
       rp.ntiles = (int)((rp.N + tsites - 1) / tsites);
       if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31)) {

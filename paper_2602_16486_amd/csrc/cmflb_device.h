@@ -78,6 +78,21 @@ struct D3Q27 {
       26};          // P2 P2 P2
 };
 
+// D3Q19 (Sec. 2.4): {-1, 0, 1}^3 without the eight corners, in the D3Q27
+// order above with the corners left out.  Its basis is not a tensor
+// product; the transforms are in cmflb_d3q19.h.
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int D = 3;
+  static constexpr int NT = 19;
+  static constexpr int FIRST_NOISY = 4; // I~_0-3 = 0, I~_4-18 = 1 (Sec. 2.4)
+  static constexpr int NNOISE = 15;
+  static constexpr int NBLOCKS = 4;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+};
+
 // tensor position (c_x + 1) + 3 (c_y + 1) [+ 9 (c_z + 1) in 3-D] of
 // population i
 template <class L>

@@ -21,6 +21,7 @@
 // (BX = blockDim.x, a multiple of 64); a block walks tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ... and keeps its statistics in
 // registers until the end, so the partial-sum traffic is one row per block.
+#include "cmflb_d3q19.h"
 #include "cmflb_device.h"
 #include "cmflb_internal.h"
 
@@ -51,9 +52,9 @@ __device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
 // lam, noise, replica, key0, key1): the single-lattice kernel passes its
 // kernel argument, the ensemble kernel a replica record in global memory.
 template <class L, typename R, bool GENERAL, class P>
-__device__ __forceinline__ void collide_site(R *d, const P &p,
-                                             uint32_t site, uint32_t step,
-                                             Acc &acc) {
+__device__ __forceinline__ void collide_tensor(R *d, const P &p,
+                                               uint32_t site, uint32_t step,
+                                               Acc &acc) {
   constexpr int Q = L::Q;
   // step 1: rho = rho0 + sum d, rho u = sum c d (eq. macro).  D3Q27 forms
   // them from per-row partial sums (sum and difference along x of each
@@ -233,6 +234,86 @@ __device__ __forceinline__ void collide_site(R *d, const P &p,
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = t[pop_pos<L>(i)];
+}
+
+// D3Q19 (Sec. 2.4): r = M d (basis raw moments of the deviations), then the
+// same steps with k = N(u) r and f* = M^-1 N(u)^-1 k* (cmflb_d3q19.h).  With
+// the paper's rates only k_7..k_9 = r_7..r_9 - rho u_a u_b are needed
+// (M_7 = c_x c_y, M_8 = c_y c_z, M_9 = c_x c_z); k_eq = (rho, 0, ..., 0).
+template <typename R, bool GENERAL, class P>
+__device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
+                                              uint32_t step, Acc &acc) {
+  using L = D3Q19;
+  R r[19];
+  d3q19::raw_moments(d, r);
+  const R drho = r[0], jx = r[1], jy = r[2], jz = r[3];
+  const R rho = p.rho0 + drho;
+  const R irho = R(1) / rho;
+  const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
+
+  acc.v[0] += (double)drho;
+  acc.v[1] += (double)jx;
+  acc.v[2] += (double)jy;
+  acc.v[3] += (double)jz;
+  acc.v[4] += (double)ux;
+  acc.v[5] += (double)uy;
+  acc.v[6] += (double)uz;
+  acc.v[7] += (double)(ux * ux);
+  acc.v[8] += (double)(uy * uy);
+  acc.v[9] += (double)(uz * uz);
+  acc.v[10] += finite4(rho, ux, uy, uz) ? 0.0 : 1.0;
+
+  R eta[L::NNOISE];
+  if (p.noise) {
+    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, eta);
+  } else {
+#pragma unroll
+    for (int n = 0; n < L::NNOISE; ++n) eta[n] = R(0);
+  }
+  const R sq = sqrt(rho);
+
+  R k[19];
+  if constexpr (!GENERAL) {
+    const R k7 = r[7] - jx * uy, k8 = r[8] - jy * uz, k9 = r[9] - jx * uz;
+    k[0] = rho;
+    k[1] = R(0);
+    k[2] = R(0);
+    k[3] = R(0);
+#pragma unroll
+    for (int n = 0; n < L::NNOISE; ++n) {
+      const int v = L::FIRST_NOISY + n;
+      R val = p.amp[v] * sq * eta[n];
+      if (v == 7) val += p.oml[7] * k7;
+      if (v == 8) val += p.oml[8] * k8;
+      if (v == 9) val += p.oml[9] * k9;
+      k[v] = val;
+    }
+  } else {
+    // raw moments of f = d + w rho0 differ from those of d in r_0 only
+    r[0] = rho;
+    d3q19::shift_forward(r, ux, uy, uz);
+#pragma unroll
+    for (int v = 0; v < 19; ++v) {
+      R val = p.oml[v] * r[v];
+      if (v == 0) val += p.lam[0] * rho;
+      if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+      k[v] = val;
+    }
+  }
+  // raw moments of f*, then those of d* = f* - w rho0 (r_0 only: k*_0 - rho0
+  // = drho, set directly as in the tensor lattices), then the populations
+  d3q19::shift_inverse(k, ux, uy, uz);
+  k[0] = drho;
+  d3q19::populations(k, d);
+}
+
+template <class L, typename R, bool GENERAL, class P>
+__device__ __forceinline__ void collide_site(R *d, const P &p, uint32_t site,
+                                             uint32_t step, Acc &acc) {
+  if constexpr (L::Q == 19)
+    collide_d3q19<R, GENERAL>(d, p, site, step, acc);
+  else
+    collide_tensor<L, R, GENERAL>(d, p, site, step, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,13 +573,24 @@ __global__ __launch_bounds__(256) void k_init_eq(const ConvParams cp,
 #pragma unroll
   for (int k = 0; k < L::NT; ++k) t[k] = 0.0;
   t[0] = r;
-  add_rest_moments<L::D, double>(t, -cp.rho0, ux, uy, uz);
-  const Axis<double> ax(ux), ay(uy), az(uz);
-  tensor_inv<L::D, double>(t, ax, ay, az);
+  if constexpr (L::Q == 19) {
+    double dd[19];
+    d3q19::shift_inverse(t, ux, uy, uz);
+    t[0] = r - cp.rho0;
+    d3q19::populations(t, dd);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
-              t[pop_pos<L>(i)], cp.iscale[i]);
+    for (int i = 0; i < L::Q; ++i)
+      ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)), dd[i],
+                cp.iscale[i]);
+  } else {
+    add_rest_moments<L::D, double>(t, -cp.rho0, ux, uy, uz);
+    const Axis<double> ax(ux), ay(uy), az(uz);
+    tensor_inv<L::D, double>(t, ax, ay, az);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+      ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+                t[pop_pos<L>(i)], cp.iscale[i]);
+  }
 }
 
 template <class L, typename S>
@@ -855,7 +947,7 @@ __global__ __launch_bounds__(256) void k_vel_hist(const ConvParams cp,
 // A tile is spt x kEnsembleBlock consecutive sites (x fastest) of one
 // replica, so every lane of a workgroup is busy whatever the box edges; the
 // replica, and with it the lattice type, is uniform per workgroup.
-// Replicas are listed D3Q27 first (heavier tiles dispatched first).
+// Replicas are listed 3-D first (heavier tiles dispatched first).
 template <class L, typename S, typename R, bool GENERAL, bool NT>
 __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
                                               S *__restrict__ dst,
@@ -905,6 +997,11 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
       if (s < p.nsites) ensemble_site<D3Q27, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+    }
+  } else if (p.q == 19) {
+    for (int j = 0; j < p.spt; ++j) {
+      const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
+      if (s < p.nsites) ensemble_site<D3Q19, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   } else {
     for (int j = 0; j < p.spt; ++j) {
@@ -1000,6 +1097,9 @@ hipError_t launch_step(int q, int storage, bool general, bool nt,
   if (q == 9)
     return step_l<D2Q9>(storage, general, nt, params, src, dst, step_ptr, step_off,
                         partials, grid, block, stream);
+  if (q == 19)
+    return step_l<D3Q19>(storage, general, nt, params, src, dst, step_ptr, step_off,
+                         partials, grid, block, stream);
   if (q == 27)
     return step_l<D3Q27>(storage, general, nt, params, src, dst, step_ptr, step_off,
                          partials, grid, block, stream);
@@ -1046,6 +1146,7 @@ hipError_t with_lattice_storage(int q, int storage, F &&f) {
     return hipErrorInvalidValue;
   };
   if (q == 9) return by_storage(Tag<D2Q9>{});
+  if (q == 19) return by_storage(Tag<D3Q19>{});
   if (q == 27) return by_storage(Tag<D3Q27>{});
   return hipErrorInvalidValue;
 }
@@ -1136,6 +1237,13 @@ hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
                          key0, key1, replica, step, site0, n, out);
     else
       hipLaunchKernelGGL((k_noise<D2Q9, float>), dim3(g), dim3(256), 0, stream,
+                         key0, key1, replica, step, site0, n, out);
+  } else if (q == 19) {
+    if (fp64)
+      hipLaunchKernelGGL((k_noise<D3Q19, double>), dim3(g), dim3(256), 0,
+                         stream, key0, key1, replica, step, site0, n, out);
+    else
+      hipLaunchKernelGGL((k_noise<D3Q19, float>), dim3(g), dim3(256), 0, stream,
                          key0, key1, replica, step, site0, n, out);
   } else if (q == 27) {
     if (fp64)

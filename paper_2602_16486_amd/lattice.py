@@ -11,15 +11,17 @@ from . import _lib
 
 def rate_vector(q, tau, kind="paper"):
     """Per-mode relaxation rates Lambda_v, in the mode order of the paper's
-    bases (Sec. 2.2 for D2Q9, Sec. 2.3 for D3Q27), omega = 1 / tau.
+    bases (Sec. 2.2 for D2Q9, Sec. 2.3 for D3Q27, Sec. 2.4 for D3Q19),
+    omega = 1 / tau.
 
     * ``paper``: the printed rates -- D2Q9 Lambda_4 = Lambda_5 = omega, D3Q27
-      Lambda_7..9 = omega, every other mode 1.  On D3Q27 the diagonal
-      second-order modes (4..6) then relax at 1, so normal-stress differences
-      diffuse with nu = c_s^2 (1 - 1/2) = 1/6 whatever tau is, and only the
-      off-diagonal shear follows c_s^2 (tau - 1/2).
-    * ``isotropic``: D3Q27 with Lambda_4..9 = omega (one shear viscosity for
-      every second-order mode, bulk included); on D2Q9 the paper's rates,
+      and D3Q19 Lambda_7..9 = omega, every other mode 1.  On the 3-D lattices
+      the diagonal second-order modes (4..6) then relax at 1, so
+      normal-stress differences diffuse with nu = c_s^2 (1 - 1/2) = 1/6
+      whatever tau is, and only the off-diagonal shear follows
+      c_s^2 (tau - 1/2).
+    * ``isotropic``: 3-D lattices with Lambda_4..9 = omega (one viscosity
+      for every second-order mode, bulk included); on D2Q9 the paper's rates,
       which are already isotropic.
     * ``single``: Lambda_v = omega for every mode (single-rate comparator of
       Test 6).

@@ -45,7 +45,7 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw,msg", [
-    ({"q": 10}, "q must be 9 or 27"),
+    ({"q": 10}, "q must be 9, 19 or 27"),
     ({"q": 9, "nz": 2}, "D2Q9 needs nz = 1"),
     ({"nx": 0}, "box edges"),
     ({"q": 27, "nx": 2048, "ny": 1024, "nz": 1024}, "exceeds 2^31"),

@@ -78,8 +78,8 @@ def test_taylor_green_fp32_within_rounding_accumulation_of_fp64():
         assert np.abs(_velocity(9, f32) - _velocity(9, f64)).max() <= bound, n
 
 
-def _tg3_gpu(n, tau, kind, storage, t1=20, t2=80):
-    q, shape = 27, (n, n, 2)
+def _tg3_gpu(q, n, tau, kind, storage, t1=20, t2=80):
+    shape = (n, n, 2)
     kappa = 2 * math.pi / n
     u = W.taylor_green(shape, 1e-3)
     lam = rate_vector(q, tau, kind)
@@ -96,19 +96,21 @@ def _tg3_gpu(n, tau, kind, storage, t1=20, t2=80):
     return math.log(amp[0] / amp[1]) / (2 * kappa ** 2 * (t2 - t1)), f, lam
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("tau", [0.6, 1.2])
-def test_d3q27_rate_readings_viscosity_on_gpu(storage, tau):
-    """Literal D3Q27 rates (Lambda_4-6 = 1): the axis-aligned vortex decays
-    with nu = 1/6 for any tau; isotropic rates (Lambda_4-9 = omega, general
-    kernel): nu = c_s^2 (tau - 1/2).  FP64 populations equal the oracle's."""
-    nu_p, f_p, lam_p = _tg3_gpu(24, tau, "paper", storage)
-    nu_i, f_i, lam_i = _tg3_gpu(24, tau, "isotropic", storage)
+def test_3d_rate_readings_viscosity_on_gpu(q, storage, tau):
+    """Literal D3Q27 / D3Q19 rates (Lambda_4-6 = 1): the axis-aligned vortex
+    decays with nu = 1/6 for any tau; isotropic rates (Lambda_4-9 = omega,
+    general kernel): nu = c_s^2 (tau - 1/2).  FP64 populations equal the
+    oracle's."""
+    nu_p, f_p, lam_p = _tg3_gpu(q, 24, tau, "paper", storage)
+    nu_i, f_i, lam_i = _tg3_gpu(q, 24, tau, "isotropic", storage)
     assert abs(nu_p * 6 - 1) < 0.01
     assert abs(nu_i / ((tau - 0.5) / 3) - 1) < 0.02
     if storage == "f64":
         shape = (24, 24, 2)
         for f_gpu, lam in ((f_p, lam_p), (f_i, lam_i)):
-            f = O.init_equilibrium(27, 24 * 24 * 2, rho0=1.0, u=W.taylor_green(shape, 1e-3))
-            O.run(27, shape, f, 0.0, lam, seed=0, nsteps=80)
+            f = O.init_equilibrium(q, 24 * 24 * 2, rho0=1.0, u=W.taylor_green(shape, 1e-3))
+            O.run(q, shape, f, 0.0, lam, seed=0, nsteps=80)
             assert np.abs(f_gpu - f).max() <= 80 * 2.0 ** -52 * np.abs(f).max()

@@ -16,6 +16,7 @@ REPLICAS = [
     {"q": 9, "shape": (300, 5), "kT": 1e-5, "tau": 1.9, "seed": 13, "replica": 2, "rho0": 1.3},
     {"q": 27, "shape": (20, 18, 16), "kT": 1e-3, "tau": 0.9, "seed": 14, "replica": 3},
     {"q": 9, "shape": (64, 64), "kT": 0.0, "tau": 0.8, "seed": 15, "replica": 4},
+    {"q": 19, "shape": (11, 10, 9), "kT": 2e-4, "tau": 0.65, "seed": 16, "replica": 5},
 ]
 
 

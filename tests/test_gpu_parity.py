@@ -60,7 +60,7 @@ def test_philox_words_bit_exact():
         assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("q", [9, 27])
+@pytest.mark.parametrize("q", [9, 19, 27])
 @pytest.mark.parametrize("fp64", [False, True])
 def test_normals_match_oracle(q, fp64):
     n, site0, step, seed, replica = 3000, 123456, 77, (1 << 40) + 5, 3
@@ -72,7 +72,7 @@ def test_normals_match_oracle(q, fp64):
 
 # ---- state conversion -----------------------------------------------------
 
-@pytest.mark.parametrize("q,shape", [(9, (37, 23)), (27, (13, 9, 7))])
+@pytest.mark.parametrize("q,shape", [(9, (37, 23)), (19, (11, 9, 7)), (27, (13, 9, 7))])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_init_equilibrium_matches_oracle(q, shape, storage):
     n = W.n_sites(shape)
@@ -86,7 +86,7 @@ def test_init_equilibrium_matches_oracle(q, shape, storage):
     assert _rel_err(got, ref, q) < tol
 
 
-@pytest.mark.parametrize("q,shape", [(9, (300, 5)), (27, (70, 6, 5))])
+@pytest.mark.parametrize("q,shape", [(9, (300, 5)), (19, (70, 6, 5)), (27, (70, 6, 5))])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_set_get_roundtrip(q, shape, storage):
     f = _random_state(q, shape, 9)
@@ -110,7 +110,8 @@ def test_set_get_roundtrip(q, shape, storage):
 
 # ---- one step and many steps ---------------------------------------------
 
-@pytest.mark.parametrize("q,shape", [(9, (300, 7)), (27, (300, 4, 3)), (27, (37, 5, 6))])
+@pytest.mark.parametrize("q,shape", [(9, (300, 7)), (19, (300, 4, 3)), (19, (37, 5, 6)), (27, (300, 4, 3)),
+                                     (27, (37, 5, 6))])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("general", [False, True])
 def test_one_step_matches_oracle(q, shape, storage, general):
@@ -167,10 +168,11 @@ def test_config1_prefix_matches_oracle(storage):
     assert np.abs(st[:, 1] - ref[:, 1]).max() < (1e-9 if storage == "f64" else f32_mass)
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("general", [False, True])
-def test_d3q27_multistep_matches_oracle(storage, general):
-    q, shape, kT, steps = 27, (20, 18, 16), 1e-4, 12
+def test_3d_multistep_matches_oracle(q, storage, general):
+    shape, kT, steps = (20, 18, 16), 1e-4, 12
     f0 = _random_state(q, shape, 31, umax=0.04)
     lam = np.full(q, 1 / 0.55) if general else None
     lam_o = lam if general else O.paper_lambda(q, 1 / 0.55)
@@ -182,13 +184,13 @@ def test_d3q27_multistep_matches_oracle(storage, general):
     O.run(q, shape, f, kT, lam_o, 7, 0, 0, steps)
     tol = F64_TOL if storage == "f64" else F32_TOL(steps)
     err = _rel_err(got, f, q)
-    print(f"d3q27 {storage} general={general}: rel err {err:.3e} (tol {tol:.1e})")
+    print(f"d3q{q} {storage} general={general}: rel err {err:.3e} (tol {tol:.1e})")
     assert err < tol
 
 
 # ---- invariants of the implementation -------------------------------------
 
-@pytest.mark.parametrize("q,shape", [(9, (40, 30)), (27, (12, 10, 8))])
+@pytest.mark.parametrize("q,shape", [(9, (40, 30)), (19, (12, 10, 8)), (27, (12, 10, 8))])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_zero_noise_rest_state_is_exact(q, shape, storage):
     """Test 1: kT = 0 from rest stays exactly at rest (deviations stay 0)."""
