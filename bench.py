@@ -31,9 +31,9 @@ TAU, KT, RHO0, SEED = 0.8, 1e-4, 1.0, 1
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def bytes_per_site(storage):
+def bytes_per_site(storage, q=Q):
     # every population read once and written once per step
-    return 2 * Q * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    return 2 * q * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
 
 
 def log(msg):
@@ -68,10 +68,10 @@ def measured_traffic(launch):
     return c["traffic_bytes_per_launch"]
 
 
-def time_storage(storage, steps, warmup, stream, torch, tune=True):
+def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
     from paper_2602_16486_amd import Lattice
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
-    with Lattice(Q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
+    with Lattice(q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
                  stream=stream.cuda_stream, series_capacity=8192) as lat:
         if tune:
             lat.autotune(steps_per_trial=10)  # untimed; state restored
@@ -99,7 +99,7 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True):
         "ms_per_step": ms_step,
         "glups": glups,
         "kernel_ms": kernel_ms,
-        "kernel_gbs": bytes_per_site(storage) * n / (kernel_ms * 1e-3) / 1e9,
+        "kernel_gbs": bytes_per_site(storage, q) * n / (kernel_ms * 1e-3) / 1e9,
         "u2_over_kT": float(u2.mean() * RHO0 / KT),
         "u2_series": u2,
         "nonfinite": float(st[:, 11].sum()),
@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--d3q19", default="f32,f16",
+                    help="storages of the D3Q19 256^3 lines (empty: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -237,6 +239,18 @@ def main():
             "u2_over_kT": r["u2_over_kT"], "u2_rel_diff_vs_f32": du,
         }
         log(f"{storage}: {r['glups']:.2f} GLUPS, <u2> rel diff vs f32 {du:.2e}")
+
+    lattices = {}
+    for storage in [s for s in args.d3q19.split(",") if s]:
+        log(f"timing D3Q19 {storage}")
+        r = time_storage(storage, args.steps, args.warmup, stream, torch, tune=not args.no_tune, q=19)
+        lattices[f"d3q19_{storage}"] = {
+            "value": r["glups"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+            "kernel_gbs": r["kernel_gbs"], "frac_hbm": r["kernel_gbs"] / PEAK_HBM_GBS,
+            "launch": list(r["launch"]), "bytes_per_site": bytes_per_site(storage, 19),
+            "u2_over_kT": r["u2_over_kT"],
+        }
+        log(f"D3Q19 {storage}: {r['glups']:.2f} GLUPS, kernel {r['kernel_gbs']:.0f} GB/s")
 
     copy_bytes = Q * n * 4  # one FP32 population buffer: the step's footprint
     copy_ms = _lib.stream_copy(copy_bytes, reps=5)
@@ -277,6 +291,7 @@ def main():
         },
         "u2_over_kT": main_run["u2_over_kT"],
         "variants": variants,
+        "lattices": lattices,
     }
     if not args.no_ensemble:
         log("timing the batched ensemble (256 D2Q9 + 64 D3Q27 replicas)")

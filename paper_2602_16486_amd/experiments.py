@@ -4,8 +4,8 @@ synthetic rest-state inputs.  Each run prints one JSON line.
 
     python -m paper_2602_16486_amd.experiments NAME [--scale S]
 
-NAME: test2 tg3d test3 test4 test5 test6 test7 config2 config3 config4 config5, or
-all.
+NAME: test2 tg3d test3 test4 test5 test6 test7 d3q19 config2 config3 config4
+config5, or all.
 --scale multiplies the number of steps (default 1; the paper's durations
 are used at scale 1 where they are stated).
 """
@@ -204,6 +204,17 @@ def test7(scale):
                "paper_table3": paper[name]})
 
 
+def d3q19(scale):
+    """The D3Q19 lattice of Sec. 2.4 (the paper constructs it but runs no
+    test on it): the Test 7 boxes C1-C4 at kT = 1/3000, tau = 0.8, T = 100 t0,
+    with the Test 7 quantities and the velocity PDFs of the final state."""
+    boxes = {"C1": (50, 50, 50), "C2": (25, 50, 100), "C3": (60, 15, 30), "C4": (20, 80, 40)}
+    for name, shape in boxes.items():
+        steps = int(100 * shape[1] / 0.01 * scale)
+        r = run(19, shape, steps=steps, tau=0.8, kT=1 / 3000, window=0.99, pdf_bins=40)
+        _emit({"experiment": "d3q19", "box": name, "shape": shape, "steps": steps, **r})
+
+
 def config2(scale):
     """D2Q9 1024^2, FP32 and FP64 storage, kT x tau grid, 20000 steps,
     averages and S(k) (every 100 steps) over steps 10000-20000."""
@@ -285,8 +296,8 @@ def config5(scale):
            "replicas_within_band": int(inband), "outside_band": outliers})
 
 
-EXPERIMENTS = {f.__name__: f for f in (test2, tg3d, test3, test4, test5, test6, test7, config2, config3, config4,
-                                        config5)}
+EXPERIMENTS = {f.__name__: f for f in (test2, tg3d, test3, test4, test5, test6, test7, d3q19, config2, config3,
+                                        config4, config5)}
 
 
 def main(argv=None):
