@@ -105,6 +105,17 @@ void mode_norms(int q, double *b) {
   }
 }
 
+// the compile-time sqrt(b_v) of the kernels against the norms computed here
+bool sqrt_norms_consistent(int q) {
+  double b[27];
+  mode_norms(q, b);
+  for (int v = 0; v < q; ++v) {
+    const double s = q == 9 ? sqrt_norm<D2Q9>(v) : (q == 19 ? sqrt_norm<D3Q19>(v) : sqrt_norm<D3Q27>(v));
+    if (fabs(s * s - b[v]) > 1e-14 * b[v]) return false;
+  }
+  return true;
+}
+
 bool is_omega_mode(int q, int v) {
   return q == 9 ? (v == 4 || v == 5) : (v >= 7 && v <= 9);
 }
@@ -297,6 +308,25 @@ struct cmf_lattice {
 
 namespace {
 
+// weight class |c_i|^2 of population i of a q-velocity lattice
+int weight_class_of(int q, int i) {
+  if (q == 9) return weight_class<D2Q9>(i);
+  if (q == 19) return weight_class<D3Q19>(i);
+  return weight_class<D3Q27>(i);
+}
+
+// per-class storage scales (and reciprocals) from the per-population ones
+void class_scales(int q, const float *scale, float *cs, float *ics) {
+  for (int k = 0; k < 4; ++k) {
+    cs[k] = 1.0f;
+    ics[k] = 1.0f;
+  }
+  for (int i = 0; i < q; ++i) {
+    cs[weight_class_of(q, i)] = scale[i];
+    ics[weight_class_of(q, i)] = 1.0f / scale[i];
+  }
+}
+
 template <typename R>
 void fill_step_params(const cmf_lattice *L, const double *amp,
                       const float *scale, StepParams<R> &p) {
@@ -313,10 +343,8 @@ void fill_step_params(const cmf_lattice *L, const double *amp,
     p.oml[v] = (R)(1.0 - L->lambda[v]);
     p.lam[v] = (R)L->lambda[v];
   }
-  for (int i = 0; i < L->q; ++i) {
-    p.scale[i] = scale[i];
-    p.iscale[i] = 1.0f / scale[i];
-  }
+  p.amp1 = (R)sqrt(L->desc.kT / kCs2);
+  class_scales(L->q, scale, p.scale, p.iscale);
   p.key0 = (uint32_t)L->desc.seed;
   p.key1 = (uint32_t)(L->desc.seed >> 32);
   p.replica = L->desc.replica;
@@ -492,6 +520,8 @@ int validate(const cmf_desc *d) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1)
     return fail(CMF_EINVAL, "box edges must be >= 1 (%d, %d, %d)", d->nx, d->ny, d->nz);
   if (d->q == 9 && d->nz != 1) return fail(CMF_EINVAL, "D2Q9 needs nz = 1, got %d", d->nz);
+  if (!sqrt_norms_consistent(d->q))
+    return fail(CMF_EINVAL, "internal: the kernels' sqrt(b_v) table does not match the basis");
   const int64_t N = (int64_t)d->nx * d->ny * d->nz;
   if (N >= (int64_t)1 << 31) return fail(CMF_EINVAL, "N = %lld sites exceeds 2^31 - 1", (long long)N);
   if (d->nx >= (1 << 28)) return fail(CMF_EINVAL, "nx = %d is not below 2^28", d->nx);
@@ -1276,9 +1306,9 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
     p.amp[v] = (R)mc.amp[v];
     p.oml[v] = (R)(1.0 - mc.lambda[v]);
     p.lam[v] = (R)mc.lambda[v];
-    p.scale[v] = mc.scale[v];
-    p.iscale[v] = 1.0f / mc.scale[v];
   }
+  p.amp1 = (R)sqrt(d.kT / kCs2);
+  class_scales(d.q, mc.scale, p.scale, p.iscale);
 }
 
 void ens_release(cmf_ensemble *E) {

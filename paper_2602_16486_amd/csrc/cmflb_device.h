@@ -93,6 +93,44 @@ struct D3Q19 {
   static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
 };
 
+// sqrt(b_v), the square roots of the modal norms of the paper's bases, as
+// compile-time constants: the noise amplitude of a mode relaxed at rate 1 is
+// sqrt(kT / c_s^2) sqrt(b_v), so the paper-rate kernels need one runtime
+// amplitude instead of one per mode.  D3Q27: products of the one-axis norms
+// 1, 1/3, 2/9 over the mode's tensor position; D2Q9 (Sec. 2.2) and D3Q19
+// (Sec. 2.4) tabulated.
+constexpr double kSqrtAxisNorm[3] = {1.0, 0.57735026918962576, 0.47140452079103168};
+template <class L>
+__host__ __device__ constexpr double sqrt_norm(int v) {
+  if constexpr (L::Q == 27) {
+    return kSqrtAxisNorm[L::mode_pos[v] % 3] * kSqrtAxisNorm[(L::mode_pos[v] / 3) % 3] *
+           kSqrtAxisNorm[L::mode_pos[v] / 9];
+  } else if constexpr (L::Q == 9) {
+    // b = 1, 1/3, 1/3, 4/9, 4/9, 1/9, 2/27, 2/27, 4/81
+    constexpr double t[9] = {1.0, 0.57735026918962576, 0.57735026918962576,
+                             0.66666666666666667, 0.66666666666666667, 0.33333333333333333,
+                             0.27216552697590868, 0.27216552697590868, 0.22222222222222222};
+    return t[v];
+  } else {
+    // b = 1, 1/3 (x3), 2/3, 4/3, 4/9, 1/9 (x3), 2/3 (x3), 2/9 (x3), 2, 4/3, 4/9
+    constexpr double t[19] = {1.0, 0.57735026918962576, 0.57735026918962576,
+                              0.57735026918962576, 0.81649658092772603, 1.1547005383792515,
+                              0.66666666666666667, 0.33333333333333333, 0.33333333333333333,
+                              0.33333333333333333, 0.81649658092772603, 0.81649658092772603,
+                              0.81649658092772603, 0.47140452079103168, 0.47140452079103168,
+                              0.47140452079103168, 1.4142135623730951, 1.1547005383792515,
+                              0.66666666666666667};
+    return t[v];
+  }
+}
+
+// weight class |c_i|^2 of population i (the weights, and with them the
+// storage scales, depend on i through it only)
+template <class L>
+__host__ __device__ constexpr int weight_class(int i) {
+  return L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i];
+}
+
 // tensor position (c_x + 1) + 3 (c_y + 1) [+ 9 (c_z + 1) in 3-D] of
 // population i
 template <class L>

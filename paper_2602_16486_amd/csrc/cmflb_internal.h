@@ -25,9 +25,13 @@ struct StepParams {
   int32_t noise;            // kT > 0
   R rho0;
   R amp[27];   // I~_v sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2)
+  R amp1;      // sqrt(kT / c_s^2): amp_v = amp1 sqrt(b_v) when Lambda_v = 1
   R oml[27];   // 1 - Lambda_v
   R lam[27];   // Lambda_v
-  float scale[27], iscale[27];  // storage scale s_i and 1 / s_i
+  // storage scale s and 1 / s of each weight class |c_i|^2 = 0..3 (s_i
+  // depends on i through w_i only): 8 values instead of 2 q keeps them in
+  // scalar registers
+  float scale[4], iscale[4];
   uint32_t key0, key1, replica;
 };
 
@@ -43,9 +47,10 @@ struct ReplicaParams {
   int32_t spt;  // sites per thread: a tile is spt x kEnsembleBlock sites
   R rho0;
   R amp[27];
+  R amp1;
   R oml[27];
   R lam[27];
-  float scale[27], iscale[27];
+  float scale[4], iscale[4];  // per weight class, as in StepParams
 };
 
 // Parameters of the state conversion kernels (FP64 always).

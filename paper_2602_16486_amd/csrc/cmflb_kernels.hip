@@ -51,7 +51,12 @@ __device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
 // P is any parameter record with the fields of StepParams (rho0, amp, oml,
 // lam, noise, replica, key0, key1): the single-lattice kernel passes its
 // kernel argument, the ensemble kernel a replica record in global memory.
-template <class L, typename R, bool GENERAL, class P>
+// LEAN (16-bit storage, issue-bound): the noise amplitude of a mode relaxed
+// at rate 1 is formed as amp1 sqrt(b_v) with sqrt(b_v) a compile-time
+// constant, instead of being kept per mode in scalar registers (which then
+// spill into vector lanes); the wider storages, bound by HBM, measured
+// slightly faster with the per-mode values.
+template <class L, typename R, bool GENERAL, bool LEAN, class P>
 __device__ __forceinline__ void collide_tensor(R *d, const P &p,
                                                uint32_t site, uint32_t step,
                                                Acc &acc) {
@@ -136,13 +141,21 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       t[1] = R(0);
       t[3] = R(0);
       t[9] = R(0);
+      const R a1 = p.amp1 * sq;
 #pragma unroll
       for (int n = 0; n < L::NNOISE; ++n) {
         const int v = L::FIRST_NOISY + n;
-        R val = p.amp[v] * sq * eta[n];
-        if (v == 7) val += p.oml[7] * k7;
-        if (v == 8) val += p.oml[8] * k8;
-        if (v == 9) val += p.oml[9] * k9;
+        R val;
+        if (v == 7)
+          val = p.oml[7] * k7 + p.amp[7] * sq * eta[n];
+        else if (v == 8)
+          val = p.oml[8] * k8 + p.amp[8] * sq * eta[n];
+        else if (v == 9)
+          val = p.oml[9] * k9 + p.amp[9] * sq * eta[n];
+        else if constexpr (LEAN)
+          val = a1 * R(sqrt_norm<L>(v)) * eta[n];
+        else
+          val = p.amp[v] * sq * eta[n];
         t[L::mode_pos[v]] = val;
       }
     } else {
@@ -159,7 +172,9 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       // k_4 = r_4 - rho (u_x^2 - u_y^2), k_5 = r_5 - rho u_x u_y (Sec. 2.2)
       const R k4 = sd - (jx * ux - jy * uy);
       const R k5 = sxy - jx * uy;
-      const R k3s = p.amp[3] * sq * eta[0];
+      const R a1 = p.amp1 * sq;
+      auto amp_eta = [&](int v, R e) { return LEAN ? a1 * R(sqrt_norm<L>(v)) * e : p.amp[v] * sq * e; };
+      const R k3s = amp_eta(3, eta[0]);
       const R k4s = p.oml[4] * k4 + p.amp[4] * sq * eta[1];
       const R k5s = p.oml[5] * k5 + p.amp[5] * sq * eta[2];
       t[0] = rho;
@@ -168,9 +183,9 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       t[2] = R(0.5) * (k3s + k4s);  // P2(x) P0(y)
       t[6] = R(0.5) * (k3s - k4s);  // P0(x) P2(y)
       t[4] = k5s;
-      t[5] = p.amp[6] * sq * eta[3];
-      t[7] = p.amp[7] * sq * eta[4];
-      t[8] = p.amp[8] * sq * eta[5];
+      t[5] = amp_eta(6, eta[3]);
+      t[7] = amp_eta(7, eta[4]);
+      t[8] = amp_eta(8, eta[5]);
     }
   } else {
     // steps 3-4 for arbitrary rates: k = T(u) f = T(u) d + rho0 G(u), then
@@ -240,7 +255,7 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
 // same steps with k = N(u) r and f* = M^-1 N(u)^-1 k* (cmflb_d3q19.h).  With
 // the paper's rates only k_7..k_9 = r_7..r_9 - rho u_a u_b are needed
 // (M_7 = c_x c_y, M_8 = c_y c_z, M_9 = c_x c_z); k_eq = (rho, 0, ..., 0).
-template <typename R, bool GENERAL, class P>
+template <typename R, bool GENERAL, bool LEAN, class P>
 __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
                                               uint32_t step, Acc &acc) {
   using L = D3Q19;
@@ -279,13 +294,21 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
     k[1] = R(0);
     k[2] = R(0);
     k[3] = R(0);
+    const R a1 = p.amp1 * sq;
 #pragma unroll
     for (int n = 0; n < L::NNOISE; ++n) {
       const int v = L::FIRST_NOISY + n;
-      R val = p.amp[v] * sq * eta[n];
-      if (v == 7) val += p.oml[7] * k7;
-      if (v == 8) val += p.oml[8] * k8;
-      if (v == 9) val += p.oml[9] * k9;
+      R val;
+      if (v == 7)
+        val = p.oml[7] * k7 + p.amp[7] * sq * eta[n];
+      else if (v == 8)
+        val = p.oml[8] * k8 + p.amp[8] * sq * eta[n];
+      else if (v == 9)
+        val = p.oml[9] * k9 + p.amp[9] * sq * eta[n];
+      else if constexpr (LEAN)
+        val = a1 * R(sqrt_norm<L>(v)) * eta[n];
+      else
+        val = p.amp[v] * sq * eta[n];
       k[v] = val;
     }
   } else {
@@ -307,13 +330,13 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
   d3q19::populations(k, d);
 }
 
-template <class L, typename R, bool GENERAL, class P>
+template <class L, typename R, bool GENERAL, bool LEAN, class P>
 __device__ __forceinline__ void collide_site(R *d, const P &p, uint32_t site,
                                              uint32_t step, Acc &acc) {
   if constexpr (L::Q == 19)
-    collide_d3q19<R, GENERAL>(d, p, site, step, acc);
+    collide_d3q19<R, GENERAL, LEAN>(d, p, site, step, acc);
   else
-    collide_tensor<L, R, GENERAL>(d, p, site, step, acc);
+    collide_tensor<L, R, GENERAL, LEAN>(d, p, site, step, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +414,7 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
-      d[i] = ST::load(base + xs[L::cx[i] + 1], scale[i]);
+      d[i] = ST::load(base + xs[L::cx[i] + 1], scale[weight_class<L>(i)]);
     }
   } else {
     constexpr uint32_t B = sizeof(S);
@@ -408,7 +431,7 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const uint32_t e = sblk[L::cy[i] + 1][L::cz[i] + 1] + (uint32_t)i * unx + xs[L::cx[i] + 1];
-      d[i] = ST::load(at_byte(src, e * B), scale[i]);
+      d[i] = ST::load(at_byte(src, e * B), scale[weight_class<L>(i)]);
     }
   }
 }
@@ -424,7 +447,7 @@ __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       S *base = dst + pop_row_offset<L::Q>(i, row, nx);
-      ST::template store<NT>(base + (uint32_t)x, d[i], iscale[i]);
+      ST::template store<NT>(base + (uint32_t)x, d[i], iscale[weight_class<L>(i)]);
     }
   } else {
     constexpr uint32_t B = sizeof(S);
@@ -432,7 +455,8 @@ __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
     const uint32_t blk = (uint32_t)row * (uint32_t)L::Q * unx + (uint32_t)x;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-      ST::template store<NT>(at_byte(dst, (blk + (uint32_t)i * unx) * B), d[i], iscale[i]);
+      ST::template store<NT>(at_byte(dst, (blk + (uint32_t)i * unx) * B), d[i],
+                             iscale[weight_class<L>(i)]);
   }
 }
 
@@ -465,7 +489,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
       load_site<L, S, R, false>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
-      collide_site<L, R, GENERAL>(d, p, (uint32_t)site, step, acc);
+      collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, (uint32_t)site, step, acc);
       store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
     }
   }
@@ -962,7 +986,7 @@ __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
   const int z = (int)(row / ny);
   R d[L::Q];
   load_site<L, S, R, true>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
-  collide_site<L, R, GENERAL>(d, p, us, step, acc);
+  collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);
   store_site<L, S, R, true, NT>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
 }
 
