@@ -336,7 +336,8 @@ def test_get_macro_matches_populations(q, shape, storage):
 
 
 @pytest.mark.parametrize("q,shape,storage,steps", [(9, (40, 30), "f64", 0), (27, (12, 10, 9), "f64", 0),
-                                                   (27, (12, 10, 9), "f64", 4), (9, (64, 48), "f32", 0)])
+                                                   (27, (12, 10, 9), "f64", 4), (19, (12, 10, 9), "f64", 4),
+                                                   (9, (64, 48), "f32", 0)])
 def test_velocity_pdf_matches_oracle(q, shape, storage, steps):
     """cmf_velocity_pdf (Test 7, Fig. 8) against the oracle's plain
     definitions on the same state: moments to FP64 (FP32 storage: to the

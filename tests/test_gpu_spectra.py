@@ -17,7 +17,7 @@ def _gpu_present():
     assert _lib.device_count() > 0, "no HIP device visible: the gpu tests need an MI355X"
 
 
-@pytest.mark.parametrize("q,shape", [(9, (32, 24)), (27, (12, 10, 8)), (27, (9, 7, 5))])
+@pytest.mark.parametrize("q,shape", [(9, (32, 24)), (19, (12, 10, 8)), (27, (12, 10, 8)), (27, (9, 7, 5))])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_structure_factor_matches_oracle(q, shape, storage):
     kT, tau, seed, nbins = 2e-4, 0.8, 5, 12
