@@ -42,7 +42,8 @@ def log(msg):
 
 KERNEL_SOURCES = ("paper_2602_16486_amd/csrc/cmflb_kernels.hip",
                   "paper_2602_16486_amd/csrc/cmflb_device.h",
-                  "paper_2602_16486_amd/csrc/cmflb_internal.h")
+                  "paper_2602_16486_amd/csrc/cmflb_internal.h",
+                  "paper_2602_16486_amd/csrc/cmflb_d3q19.h")
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_d3q27_f32_256cube.counters.json")
 
 
