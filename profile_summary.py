@@ -34,7 +34,7 @@ ALG_BYTES = 2 * 27 * 4 * N
 COPY_BYTES = 27 * N * 4  # per direction
 
 CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv "
-             "-- python3 bench.py --steps 50 --warmup 32 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
+             "-- python3 bench.py --steps 400 --warmup 64 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
 CMD_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv "
              "-- python3 bench.py --steps 10 --warmup 32 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
 CMD_WRITE = CMD_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("prof_fetch", "prof_write").replace(
