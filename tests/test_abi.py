@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 from paper_2602_16486_amd import _lib
@@ -85,3 +86,41 @@ def test_missing_library_fails_loudly(tmp_path):
                                       str(tmp_path / "absent.so")))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert "raised" in out.stdout and "no CPU fallback" in out.stdout
+
+
+def test_external_buffer_validation_before_any_device_call():
+    """cmf_external_bytes and the argument checks of cmf_create_external run
+    on the host: NULL, misaligned and too small buffers are rejected before
+    the pointer is looked at."""
+    lib = _lib.load()
+    d, _ = _lib.make_desc(27, (10, 6, 4), storage="f32")
+    need = lib.cmf_external_bytes(ctypes.byref(d))
+    assert need == 2 * ((27 * 240 * 4 + 255) // 256 * 256)
+    bad, _ = _lib.make_desc(27, (10, 6, 4), storage="f32")
+    bad.q = 11
+    assert lib.cmf_external_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    for ptr, nbytes, msg in ((0, need, b"dev_ptr is NULL"), (4096 + 64, need, b"256-byte aligned"),
+                             (4096, need - 256, b"needs")):
+        rc = lib.cmf_create_external(ctypes.byref(d), ctypes.c_void_p(ptr), nbytes, None, ctypes.byref(h))
+        assert rc == _lib.CMF_EINVAL
+        assert msg in lib.cmf_last_error()
+        assert not h.value
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_rate_presets(q):
+    from paper_2602_16486_amd import rate_vector
+    tau = 0.7
+    w = 1 / tau
+    paper = rate_vector(q, tau)
+    omega_modes = [4, 5] if q == 9 else [7, 8, 9]
+    assert np.array_equal(paper, np.where(np.isin(np.arange(q), omega_modes), w, 1.0))
+    iso = rate_vector(q, tau, "isotropic")
+    if q == 9:
+        assert np.array_equal(iso, paper)
+    else:
+        assert np.array_equal(iso, np.where((np.arange(q) >= 4) & (np.arange(q) <= 9), w, 1.0))
+    assert np.array_equal(rate_vector(q, tau, "single"), np.full(q, w))
+    with pytest.raises(ValueError):
+        rate_vector(q, tau, "bgk")
