@@ -405,7 +405,10 @@ struct Store<__half, R> {
   __device__ __forceinline__ static R load(const __half *p, float scale) {
     const unsigned short bits =
         cmf_ld(reinterpret_cast<const unsigned short *>(p));
-    return (R)(__half2float(__ushort_as_half(bits)) * scale);
+    // h s + 0 as one fused multiply-add of a half and a float operand (one
+    // v_fma_mix_f32 instead of a conversion and a multiply); the zero addend
+    // turns a -0 product into +0, which is the same deviation
+    return (R)__builtin_fmaf(__half2float(__ushort_as_half(bits)), scale, 0.0f);
   }
   template <bool NT = true>
   __device__ __forceinline__ static void store(__half *p, R v, float iscale) {
