@@ -323,10 +323,15 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
       k[v] = val;
     }
   }
-  // raw moments of f*, then those of d* = f* - w rho0 (r_0 only: k*_0 - rho0
-  // = drho, set directly as in the tensor lattices), then the populations
+  // raw moments of f* (k*_1..k*_3 are the central first moments, zero by
+  // construction, and are not read), then those of d* = f* - w rho0: r_0 =
+  // k*_0 - rho0 = drho and r_1..r_3 = rho u = j exactly (mass and momentum
+  // are conserved), set directly rather than re-rounded; then the populations
   d3q19::shift_inverse(k, ux, uy, uz);
   k[0] = drho;
+  k[1] = jx;
+  k[2] = jy;
+  k[3] = jz;
   d3q19::populations(k, d);
 }
 
