@@ -347,22 +347,35 @@ __device__ __forceinline__ void collide_site(R *d, const P &p, uint32_t site,
 // ---------------------------------------------------------------------------
 // block reduction of the statistics accumulators (fixed order)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_store_acc(Acc &acc, double *out) {
-  __shared__ double sh[kMaxBlock / 64][kNAcc];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// LDS doubles used by block_store_acc for a workgroup of nt threads
+__host__ __device__ constexpr int acc_lds_doubles(int nt) { return kNAcc * (nt + nt / 16); }
+
+// Every thread writes its kNAcc sums to LDS, accumulator-major; then
+// (accumulator, part) pairs, P = nt / 16 parts per accumulator, sum the 16
+// entries part, part + P, ..., part + 15 P (the lanes of a wave read
+// consecutive entries), and kNAcc threads add the P part sums in order.  The
+// order depends only on nt (a multiple of 16).  Compared with a butterfly of
+// wave shuffles this takes kNAcc + 2 additions per thread instead of
+// 6 kNAcc, which matters when a workgroup processes a single tile.
+__device__ __forceinline__ void block_store_acc(const Acc &acc, double *out, double *lds) {
+  const int tid = threadIdx.x, nt = blockDim.x, parts = nt >> 4;
 #pragma unroll
-  for (int k = 0; k < kNAcc; ++k) {
-    double v = acc.v[k];
+  for (int k = 0; k < kNAcc; ++k) lds[k * nt + tid] = acc.v[k];
+  __syncthreads();
+  double *part = lds + kNAcc * nt;
+  for (int w = tid; w < kNAcc * parts; w += nt) {
+    const int k = w / parts, pp = w - k * parts;
+    const double *col = lds + k * nt + pp;
+    double s = col[0];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) sh[wave][k] = v;
+    for (int j = 1; j < 16; ++j) s += col[j * parts];
+    part[w] = s;
   }
   __syncthreads();
-  const int nw = blockDim.x >> 6;
-  if (threadIdx.x < kNAcc) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
-    out[threadIdx.x] = s;
+  if (tid < kNAcc) {
+    double s = part[tid * parts];
+    for (int pp = 1; pp < parts; ++pp) s += part[tid * parts + pp];
+    out[tid] = s;
   }
 }
 
@@ -498,7 +511,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
       store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
     }
   }
-  block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride);
+  extern __shared__ double acc_lds[];
+  block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride, acc_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,7 +1052,8 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
       if (s < p.nsites) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   }
-  block_store_acc(acc, partials + (int64_t)tile * kPartStride);
+  __shared__ double acc_lds[acc_lds_doubles(kEnsembleBlock)];
+  block_store_acc(acc, partials + (int64_t)tile * kPartStride, acc_lds);
 }
 
 // per-replica fixed-order sum of its tiles' partials into its series row
@@ -1078,7 +1093,8 @@ hipError_t step_one(const void *params, const void *src, void *dst,
                     const int64_t *step_ptr, int step_off, double *partials, int grid,
                     int block, hipStream_t stream) {
   const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
-  hipLaunchKernelGGL((k_step<L, S, R, G, NT>), dim3(grid), dim3(block), 0, stream,
+  hipLaunchKernelGGL((k_step<L, S, R, G, NT>), dim3(grid), dim3(block),
+                     sizeof(double) * acc_lds_doubles(block), stream,
                      static_cast<const S *>(src), static_cast<S *>(dst), p,
                      step_ptr, step_off, partials);
   return hipGetLastError();
