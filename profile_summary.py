@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402  (kernel_source_hash, constants)
 
-STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false, true>"
+STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false, true, false>"
 COPY_KERNEL = "cmf::cmf_stream_copy_kernel"
 N = 256 ** 3
 ALG_BYTES = 2 * 27 * 4 * N
