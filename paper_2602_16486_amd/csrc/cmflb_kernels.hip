@@ -407,6 +407,30 @@ __device__ __forceinline__ void block_store_acc(const A &acc, double *out, void 
   }
 }
 
+// The same sums by a butterfly of wave shuffles (six rounds per sum), then
+// the waves' results in order.  The ensemble kernel uses this form: its
+// measured step is 4 % faster with it (1.130 vs 1.174 ms for the
+// 320-replica manifest), while the single-lattice step is faster with the
+// LDS form above.
+__device__ __forceinline__ void block_store_acc_shuffle(const Acc &acc, double *out) {
+  __shared__ double sh[kMaxBlock / 64][kNAcc];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kNAcc; ++k) {
+    double v = acc.v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wave][k] = v;
+  }
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  if (threadIdx.x < kNAcc) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
@@ -1083,8 +1107,7 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
       if (s < p.nsites) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   }
-  __shared__ double acc_lds[acc_lds_bytes<double>(kEnsembleBlock) / sizeof(double)];
-  block_store_acc(acc, partials + (int64_t)tile * kPartStride, acc_lds);
+  block_store_acc_shuffle(acc, partials + (int64_t)tile * kPartStride);
 }
 
 // per-replica fixed-order sum of its tiles' partials into its series row
