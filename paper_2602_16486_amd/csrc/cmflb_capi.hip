@@ -315,15 +315,20 @@ int weight_class_of(int q, int i) {
   return weight_class<D3Q27>(i);
 }
 
-// per-class storage scales (and reciprocals) from the per-population ones
-void class_scales(int q, const float *scale, float *cs, float *ics) {
+// per-class storage scales (and reciprocals) from the per-population ones.
+// With 16-bit storage the tensor-product lattices (D2Q9, D3Q27) hand the
+// stores 2^|c_i|^2 d*_i (their inverse one-axis maps skip the halvings), so
+// the store scale of class k carries 2^-k: the stored values are the same.
+void class_scales(int q, int storage, const float *scale, float *cs, float *ics) {
+  const bool doubled = (storage == kF16 || storage == kBF16) && q != 19;
   for (int k = 0; k < 4; ++k) {
     cs[k] = 1.0f;
-    ics[k] = 1.0f;
+    ics[k] = doubled ? ldexpf(1.0f, -k) : 1.0f;
   }
   for (int i = 0; i < q; ++i) {
-    cs[weight_class_of(q, i)] = scale[i];
-    ics[weight_class_of(q, i)] = 1.0f / scale[i];
+    const int k = weight_class_of(q, i);
+    cs[k] = scale[i];
+    ics[k] = doubled ? ldexpf(1.0f / scale[i], -k) : 1.0f / scale[i];
   }
 }
 
@@ -344,7 +349,7 @@ void fill_step_params(const cmf_lattice *L, const double *amp,
     p.lam[v] = (R)L->lambda[v];
   }
   p.amp1 = (R)sqrt(L->desc.kT / kCs2);
-  class_scales(L->q, scale, p.scale, p.iscale);
+  class_scales(L->q, L->storage, scale, p.scale, p.iscale);
   p.key0 = (uint32_t)L->desc.seed;
   p.key1 = (uint32_t)(L->desc.seed >> 32);
   p.replica = L->desc.replica;
@@ -1308,7 +1313,7 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
     p.lam[v] = (R)mc.lambda[v];
   }
   p.amp1 = (R)sqrt(d.kT / kCs2);
-  class_scales(d.q, mc.scale, p.scale, p.iscale);
+  class_scales(d.q, d.storage, mc.scale, p.scale, p.iscale);
 }
 
 void ens_release(cmf_ensemble *E) {

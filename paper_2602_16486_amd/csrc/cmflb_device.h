@@ -262,14 +262,21 @@ struct Axis {
     a1 = d - u * m0;
     a2 = s - twou * d + u2mcs2 * m0;
   }
-  // (m0, m1, m2) -> (g-, g0, g+)
+  // (m0, m1, m2) -> (g-, g0, g+); DOUBLED: (2 g-, g0, 2 g+), leaving the
+  // halving of the moving populations to the caller
+  template <bool DOUBLED = false>
   __device__ __forceinline__ void inv(R &a0, R &a1, R &a2) const {
     const R r1 = a1 + u * a0;
     const R r2 = a2 + cs2pu2 * a0 + twou * a1;
     const R g0 = a0 - r2;
-    a0 = R(0.5) * (r2 - r1);
+    if constexpr (DOUBLED) {
+      a0 = r2 - r1;
+      a2 = r2 + r1;
+    } else {
+      a0 = R(0.5) * (r2 - r1);
+      a2 = R(0.5) * (r2 + r1);
+    }
     a1 = g0;
-    a2 = R(0.5) * (r2 + r1);
   }
 };
 
@@ -292,22 +299,25 @@ __device__ __forceinline__ void tensor_fwd(R *t, const Axis<R> &ax,
   }
 }
 
-template <int D, typename R>
+// DOUBLED: every one-axis map leaves out its halving, so population i comes
+// out multiplied by 2^(|c_ix| + |c_iy| + |c_iz|) = 2^|c_i|^2, an exact power
+// of two that the 16-bit stores fold into their per-weight-class scale.
+template <int D, typename R, bool DOUBLED = false>
 __device__ __forceinline__ void tensor_inv(R *t, const Axis<R> &ax,
                                            const Axis<R> &ay,
                                            const Axis<R> &az) {
   constexpr int NZ = D == 3 ? 3 : 1;
   if constexpr (D == 3) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) az.inv(t[k], t[k + 9], t[k + 18]);
+    for (int k = 0; k < 9; ++k) az.template inv<DOUBLED>(t[k], t[k + 9], t[k + 18]);
   }
 #pragma unroll
   for (int z = 0; z < NZ; ++z)
 #pragma unroll
     for (int x = 0; x < 3; ++x)
-      ay.inv(t[x + 9 * z], t[x + 3 + 9 * z], t[x + 6 + 9 * z]);
+      ay.template inv<DOUBLED>(t[x + 9 * z], t[x + 3 + 9 * z], t[x + 6 + 9 * z]);
 #pragma unroll
-  for (int k = 0; k < 3 * NZ; ++k) ax.inv(t[3 * k], t[3 * k + 1], t[3 * k + 2]);
+  for (int k = 0; k < 3 * NZ; ++k) ax.template inv<DOUBLED>(t[3 * k], t[3 * k + 1], t[3 * k + 2]);
 }
 
 // t[p] += s * G(u)[p], G = g(u_x) (x) g(u_y) (x) g(u_z), g(u) = (1, -u, u^2)

@@ -272,11 +272,14 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
   // k*_0 - rho0 = rho - rho0 = drho exactly (mode 0 is conserved); it is set
   // directly rather than as (rho0 + drho) - rho0, which would round drho to
   // the spacing of FP32 numbers near rho0.
+  // LEAN: the one-axis maps skip their halvings, so d_i comes out as
+  // 2^|c_i|^2 d*_i; the 16-bit store scales of these lattices carry the
+  // factor 2^-|c_i|^2 (exact: the stored values are unchanged)
   add_rest_moments<L::D, R>(t, -p.rho0, ux, uy, uz);
   t[0] = drho;
   {
     const Axis<R> ax(ux), ay(uy), az(uz);
-    tensor_inv<L::D, R>(t, ax, ay, az);
+    tensor_inv<L::D, R, LEAN>(t, ax, ay, az);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = t[pop_pos<L>(i)];
