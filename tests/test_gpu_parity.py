@@ -142,6 +142,34 @@ def test_one_step_matches_oracle(q, shape, storage, general):
                        atol=1e-12 * n)
 
 
+@pytest.mark.parametrize("q,shape", [(9, (300, 7)), (19, (37, 5, 6)), (27, (37, 5, 6))])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("general", [False, True])
+def test_one_step_16bit_matches_oracle(q, shape, storage, general):
+    """16-bit storage, one step from the stored (already rounded) state: each
+    population is the oracle's within one rounding of its deviation to the
+    storage format (relative 2^-11 FP16, 2^-8 BF16) plus the FP32 collision
+    error (F32_TOL(1) of the largest deviation)."""
+    f = _random_state(q, shape, 23)
+    kT, tau, seed = 2e-4, 0.7, 5
+    lam = np.linspace(0.4, 1.9, q) if general else None
+    lam_o = lam if general else O.paper_lambda(q, 1 / tau)
+    with Lattice(q, shape, storage=storage, tau=tau, kT=kT, lam=lam, seed=seed) as lat:
+        lat.set_populations(f)
+        f0 = lat.get_populations()
+        lat.step(1)
+        got = lat.get_populations()
+    ref = f0.copy()
+    O.run(q, shape, ref, kT, lam_o, seed, 0, 0, 1)
+    _, w = O.lattice(q)
+    dev = np.abs(ref - w[:, None])
+    rel = {"f16": 2 ** -11, "bf16": 2 ** -8}[storage]
+    bound = rel * (dev + F32_TOL(1) * dev.max()) * (1 + 2 ** -8) + F32_TOL(1) * dev.max()
+    excess = (np.abs(got - ref) / bound).max()
+    print(f"16-bit one step q={q} {storage} general={general}: worst |err| / bound {excess:.3f}")
+    assert excess <= 1.0
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_config1_prefix_matches_oracle(storage):
     """D2Q9 64x64, rho0 = 1, tau = 0.8, kT = 1e-4, Philox seed 1, from rest:
