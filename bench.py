@@ -107,18 +107,22 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
     }
 
 
-def ensemble_run(steps, warmup, stream, torch, eq_steps=1000):
+def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
     """Config 5: 256 D2Q9 replicas (edges uniform in [32, 512] per axis) and
     64 D3Q27 replicas (edges uniform in [32, 96]), each with its own seed,
     kT log-uniform in [1e-6, 1e-3] and tau uniform in [0.502, 2.0], FP32,
     one launch per step; compared with the same replicas stepped one
-    lattice at a time (same kernels, separate launches)."""
+    lattice at a time (same kernels, separate launches).  The tile shape is
+    autotuned first (state restored by the tuner)."""
     import numpy as np
     from paper_2602_16486_amd import Ensemble, Lattice
     from paper_2602_16486_amd import workloads as W
     manifest = W.ensemble_manifest()
     total = sum(W.n_sites(r["shape"]) for r in manifest)
     with Ensemble(manifest, storage="f32", stream=stream.cuda_stream, series_capacity=4096) as ens:
+        if tune:
+            ens.autotune(steps_per_trial=4)
+        tiles = ens.tiles
         ens.step(warmup)
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -155,6 +159,7 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000):
     return {
         "value": total / (ms * 1e-3) / 1e9, "unit": "GLUPS", "ms_per_step": ms,
         "kernel_ms": kernel_ms, "sites": total, "replicas": len(manifest),
+        "tiles_sites_per_thread": {"d2q9": tiles[0], "3d": tiles[1]},
         "bytes_per_step": sum(W.n_sites(r["shape"]) * 2 * r["q"] * 4 for r in manifest),
         "sequential_single_replica_glups": total / (seq_ms * 1e-3) / 1e9,
         "speedup_vs_sequential": seq_ms / ms,
@@ -296,7 +301,7 @@ def main():
     }
     if not args.no_ensemble:
         log("timing the batched ensemble (256 D2Q9 + 64 D3Q27 replicas)")
-        ens = ensemble_run(min(args.steps, 200), 40, stream, torch)
+        ens = ensemble_run(min(args.steps, 200), 40, stream, torch, tune=not args.no_tune)
         ens["achieved_gbs"] = ens["bytes_per_step"] / (ens["kernel_ms"] * 1e-3) / 1e9
         result["ensemble"] = ens
         log(f"ensemble: {ens['value']:.2f} GLUPS ({ens['speedup_vs_sequential']:.2f}x the sequential runs)")

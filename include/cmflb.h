@@ -318,6 +318,40 @@ int cmf_ensemble_destroy(cmf_ensemble *ens);
 int cmf_ensemble_info(cmf_ensemble *ens, int32_t *n_replicas,
                       int64_t *total_sites, int64_t *n_tiles);
 
+/* Tile shape of the ensemble step kernel: a tile is spt x 256 consecutive
+ * sites of one replica (spt9 for D2Q9 replicas, spt3d for D3Q19 and D3Q27
+ * replicas; one workgroup of 256 threads per tile, each thread spt sites).
+ * Defaults 3 and 1 (environment variables CMF_ENSEMBLE_SPT9 and
+ * CMF_ENSEMBLE_SPT27 override them at creation). */
+typedef struct {
+  int32_t spt9;
+  int32_t spt3d;
+  double ms_per_step; /* measured by cmf_ensemble_autotune; 0 otherwise */
+} cmf_ensemble_tiles;
+
+/* Current tile shape. */
+int cmf_ensemble_get_tiles(cmf_ensemble *ens, cmf_ensemble_tiles *out);
+
+/* Set the tile shape (both values in [1, 16]).  Results do not depend on
+ * it (the noise is keyed by the site), only the speed and the summation
+ * order of the statistics.  Synchronises; rebuilds the tile map (may
+ * reallocate it and the partial sums: CMF_ENOMEM) and drops captured
+ * graphs.  Errors: CMF_EINVAL, CMF_ENOMEM, CMF_EHIP. */
+int cmf_ensemble_set_tiles(cmf_ensemble *ens, int32_t spt9, int32_t spt3d);
+
+/* Autotuner of the tile shape (the batched-ensemble configuration of the
+ * benchmark asks for tuned tiles): time spt9 in {1, 2, 3, 4, 6, 8} (when
+ * there are D2Q9 replicas) x spt3d in {1, 2, 3, 4} (when there are 3-D
+ * replicas) with `steps_per_trial` direct steps each (after one untimed
+ * step; a step = fused kernel + per-replica statistics), then restore the
+ * populations, step counter and statistics rings exactly and keep the
+ * fastest shape.  Up to `cap` trials go to `trials` (may be NULL); *n_out
+ * (may be NULL) receives their number.  Needs one temporary buffer the size
+ * of a population arena.  Synchronous.  Errors: CMF_EINVAL, CMF_ENOMEM,
+ * CMF_EHIP (the previous tile shape is kept on error). */
+int cmf_ensemble_autotune(cmf_ensemble *ens, int32_t steps_per_trial,
+                          cmf_ensemble_tiles *trials, int32_t cap, int32_t *n_out);
+
 /* Replica `index` (creation order) to f_eq(rho, u), with the arguments of
  * cmf_init_equilibrium.  The shared step counter is not changed.
  * Synchronous. */

@@ -60,6 +60,10 @@ class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
+class EnsembleTiles(ctypes.Structure):
+    _fields_ = [("spt9", ctypes.c_int32), ("spt3d", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+
+
 class Moments(ctypes.Structure):
     _fields_ = [("v", ctypes.c_double * 12)]
 
@@ -133,6 +137,10 @@ def load():
     lib.cmf_ensemble_synchronize.argtypes = [vp]
     lib.cmf_ensemble_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_ensemble_stats.argtypes = [vp, i32, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_ensemble_get_tiles.argtypes = [vp, ctypes.POINTER(EnsembleTiles)]
+    lib.cmf_ensemble_set_tiles.argtypes = [vp, i32, i32]
+    lib.cmf_ensemble_autotune.argtypes = [vp, i32, ctypes.POINTER(EnsembleTiles), i32,
+                                          ctypes.POINTER(ctypes.c_int32)]
     lib.cmf_sk_reset.argtypes = [vp, i32]
     lib.cmf_sk_accumulate.argtypes = [vp]
     lib.cmf_sk_shells.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
@@ -141,7 +149,8 @@ def load():
     for name in ("cmf_ensemble_create", "cmf_ensemble_destroy", "cmf_ensemble_info",
                  "cmf_ensemble_init_equilibrium", "cmf_ensemble_set_populations",
                  "cmf_ensemble_get_populations", "cmf_ensemble_step", "cmf_ensemble_profile_steps",
-                 "cmf_ensemble_synchronize", "cmf_ensemble_get_step", "cmf_ensemble_stats"):
+                 "cmf_ensemble_synchronize", "cmf_ensemble_get_step", "cmf_ensemble_stats",
+                 "cmf_ensemble_get_tiles", "cmf_ensemble_set_tiles", "cmf_ensemble_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cmf_get_launch", "cmf_set_launch", "cmf_autotune", "cmf_stream_copy", "cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
                  "cmf_get_populations", "cmf_gather_sites", "cmf_step", "cmf_synchronize",

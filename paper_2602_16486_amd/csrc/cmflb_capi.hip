@@ -1270,6 +1270,9 @@ struct cmf_ensemble {
   bool own_stream = false;
   hipStream_t stream = nullptr;
   std::vector<Rep> reps;
+  std::vector<ModeConstants> mcs;
+  int spt9 = kEnsembleSpt9, spt3d = kEnsembleSpt27;  // sites per thread of a tile
+  int tiles_cap = 0;  // tiles the tile map and the partials are allocated for
   void *arena[2] = {nullptr, nullptr};
   size_t arena_bytes = 0;
   int parity = 0;
@@ -1375,6 +1378,62 @@ void *ens_replica_buffer(cmf_ensemble *E, int index) {
   return (char *)E->arena[E->parity] + E->reps[index].offset * storage_bytes(E->storage);
 }
 
+// Tile the replicas with spt9 (D2Q9) / spt3d (D3Q19, D3Q27) x kEnsembleBlock
+// sites per tile: 3-D replicas first, then D2Q9, each in creation order.
+// Uploads the tile map and the replica records, grows the tile map and the
+// partial-sum buffers when needed and drops captured graphs.  The stream
+// must be idle.
+int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
+  std::vector<int32_t> tile_rep;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int r = 0; r < E->n; ++r) {
+      const int q = E->reps[r].desc.q;
+      if ((pass == 0) != (q != 9)) continue;
+      cmf_ensemble::Rep &rp = E->reps[r];
+      rp.tile0 = (int)tile_rep.size();
+      rp.spt = q == 9 ? spt9 : spt3d;
+      const int64_t tsites = (int64_t)rp.spt * kEnsembleBlock;
+      rp.ntiles = (int)((rp.N + tsites - 1) / tsites);
+      if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31))
+        return fail(CMF_EINVAL, "ensemble has too many tiles");
+      tile_rep.insert(tile_rep.end(), rp.ntiles, r);
+    }
+  const int nt = (int)tile_rep.size();
+  if (nt > E->tiles_cap) {
+    if (E->d_tile_rep) (void)hipFree(E->d_tile_rep);
+    if (E->partials) (void)hipFree(E->partials);
+    E->d_tile_rep = nullptr;
+    E->partials = nullptr;
+    E->tiles_cap = 0;
+    if (hipMalloc((void **)&E->d_tile_rep, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc((void **)&E->partials, 2 * sizeof(double) * kPartStride * nt) != hipSuccess)
+      return fail(CMF_ENOMEM, "allocation of the tile map (%d tiles) failed", nt);
+    E->tiles_cap = nt;
+  }
+  E->ntiles = nt;
+  E->spt9 = spt9;
+  E->spt3d = spt3d;
+  hipError_t e = hipMemcpy(E->d_tile_rep, tile_rep.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    if (E->storage == kF64) {
+      std::vector<ReplicaParams<double>> h(E->n);
+      for (int r = 0; r < E->n; ++r) fill_replica(E->reps[r].desc, E->mcs[r], E->reps[r], h[r]);
+      e = hipMemcpy(E->d_reps, h.data(), sizeof(ReplicaParams<double>) * E->n, hipMemcpyHostToDevice);
+    } else {
+      std::vector<ReplicaParams<float>> h(E->n);
+      for (int r = 0; r < E->n; ++r) fill_replica(E->reps[r].desc, E->mcs[r], E->reps[r], h[r]);
+      e = hipMemcpy(E->d_reps, h.data(), sizeof(ReplicaParams<float>) * E->n, hipMemcpyHostToDevice);
+    }
+  }
+  for (int k = 0; k < 2; ++k)
+    if (E->graph[k]) {
+      (void)hipGraphExecDestroy(E->graph[k]);
+      E->graph[k] = nullptr;
+    }
+  if (e != hipSuccess) return fail(CMF_EHIP, "tile map upload failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1402,7 +1461,8 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
   E->cap = descs[0].series_capacity > 0 ? descs[0].series_capacity : 4096;
   E->reps.resize(n);
   E->read_step.assign(n, 0);
-  std::vector<ModeConstants> mcs(n);
+  E->mcs.resize(n);
+  std::vector<ModeConstants> &mcs = E->mcs;
   int64_t offset = 0;
   for (int r = 0; r < n; ++r) {
     cmf_ensemble::Rep &rp = E->reps[r];
@@ -1425,27 +1485,11 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     }
     E->total_sites += rp.N;
   }
-  // sites per thread (CMF_ENSEMBLE_SPT9 / CMF_ENSEMBLE_SPT27, the latter for
-  // both 3-D lattices, override the defaults, 1..16)
+  // sites per thread of the tiles (cmf_ensemble_set_tiles / _autotune;
+  // CMF_ENSEMBLE_SPT9 / CMF_ENSEMBLE_SPT27, the latter for both 3-D
+  // lattices, override the defaults, 1..16)
   const int spt9 = env_int("CMF_ENSEMBLE_SPT9", kEnsembleSpt9, 1, 16);
   const int spt27 = env_int("CMF_ENSEMBLE_SPT27", kEnsembleSpt27, 1, 16);
-  // tiles: 3-D replicas first, then D2Q9, each in creation order
-  std::vector<int32_t> tile_rep;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int r = 0; r < n; ++r) {
-      if ((pass == 0) != (descs[r].q != 9)) continue;
-      cmf_ensemble::Rep &rp = E->reps[r];
-      rp.tile0 = (int)tile_rep.size();
-      rp.spt = descs[r].q == 9 ? spt9 : spt27;
-      const int64_t tsites = (int64_t)rp.spt * kEnsembleBlock;
-      rp.ntiles = (int)((rp.N + tsites - 1) / tsites);
-      if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31)) {
-        ens_release(E);
-        return fail(CMF_EINVAL, "ensemble has too many tiles");
-      }
-      tile_rep.insert(tile_rep.end(), rp.ntiles, r);
-    }
-  E->ntiles = (int)tile_rep.size();
   E->arena_bytes = ((size_t)offset * storage_bytes(E->storage) + 255) / 256 * 256;
   hipError_t e = hip_stream ? hipSuccess : hipStreamCreate(&E->stream);
   if (hip_stream) E->stream = (hipStream_t)hip_stream; else E->own_stream = true;
@@ -1457,8 +1501,6 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
   bool ok = hipMalloc(&E->arena[0], E->arena_bytes) == hipSuccess &&
             hipMalloc(&E->arena[1], E->arena_bytes) == hipSuccess &&
             hipMalloc(&E->d_reps, rec * n) == hipSuccess &&
-            hipMalloc((void **)&E->d_tile_rep, sizeof(int32_t) * E->ntiles) == hipSuccess &&
-            hipMalloc((void **)&E->partials, 2 * sizeof(double) * kPartStride * E->ntiles) == hipSuccess &&
             hipMalloc((void **)&E->series, sizeof(double) * kSeriesStride * E->cap * n) == hipSuccess &&
             hipMalloc((void **)&E->d_mass0, sizeof(double) * n) == hipSuccess &&
             hipMalloc((void **)&E->step_dev, sizeof(int64_t)) == hipSuccess;
@@ -1466,19 +1508,17 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     ens_release(E);
     return fail(CMF_ENOMEM, "ensemble allocation (%zu bytes per arena) failed", E->arena_bytes);
   }
+  {
+    const int rc = ens_build_tiles(E, spt9, spt27);
+    if (rc != CMF_OK) {
+      const std::string msg = g_last_error;
+      ens_release(E);
+      return fail(rc, "%s", msg.c_str());
+    }
+  }
   std::vector<double> mass0(n);
   for (int r = 0; r < n; ++r) mass0[r] = (double)E->reps[r].N * descs[r].rho0;
-  if (E->storage == kF64) {
-    std::vector<ReplicaParams<double>> h(n);
-    for (int r = 0; r < n; ++r) fill_replica(descs[r], mcs[r], E->reps[r], h[r]);
-    e = hipMemcpy(E->d_reps, h.data(), rec * n, hipMemcpyHostToDevice);
-  } else {
-    std::vector<ReplicaParams<float>> h(n);
-    for (int r = 0; r < n; ++r) fill_replica(descs[r], mcs[r], E->reps[r], h[r]);
-    e = hipMemcpy(E->d_reps, h.data(), rec * n, hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess) e = hipMemcpy(E->d_tile_rep, tile_rep.data(), sizeof(int32_t) * E->ntiles, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(E->d_mass0, mass0.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  e = hipMemcpy(E->d_mass0, mass0.data(), sizeof(double) * n, hipMemcpyHostToDevice);
   // at rest every deviation is exactly zero
   if (e == hipSuccess) e = hipMemsetAsync(E->arena[0], 0, E->arena_bytes, E->stream);
   if (e == hipSuccess) e = launch_zero_i64(E->step_dev, 1, E->stream);
@@ -1502,6 +1542,101 @@ int cmf_ensemble_info(cmf_ensemble *E, int32_t *n_replicas, int64_t *total_sites
   if (n_replicas) *n_replicas = E->n;
   if (total_sites) *total_sites = E->total_sites;
   if (n_tiles) *n_tiles = E->ntiles;
+  return CMF_OK;
+}
+
+int cmf_ensemble_get_tiles(cmf_ensemble *E, cmf_ensemble_tiles *out) {
+  if (!E || !out) return fail(CMF_EINVAL, "NULL argument");
+  out->spt9 = E->spt9;
+  out->spt3d = E->spt3d;
+  out->ms_per_step = 0.0;
+  return CMF_OK;
+}
+
+int cmf_ensemble_set_tiles(cmf_ensemble *E, int32_t spt9, int32_t spt3d) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (spt9 < 1 || spt9 > 16 || spt3d < 1 || spt3d > 16)
+    return fail(CMF_EINVAL, "sites per thread must be in [1, 16], got %d and %d", spt9, spt3d);
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  return ens_build_tiles(E, spt9, spt3d);
+}
+
+int cmf_ensemble_autotune(cmf_ensemble *E, int32_t steps_per_trial, cmf_ensemble_tiles *trials,
+                          int32_t cap, int32_t *n_out) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (steps_per_trial < 1) return fail(CMF_EINVAL, "steps_per_trial must be >= 1");
+  if (n_out) *n_out = 0;
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  bool has2d = false, has3d = false;
+  for (const auto &rp : E->reps) (rp.desc.q == 9 ? has2d : has3d) = true;
+  std::vector<int> c9 = has2d ? std::vector<int>{1, 2, 3, 4, 6, 8} : std::vector<int>{E->spt9};
+  std::vector<int> c3 = has3d ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{E->spt3d};
+  // snapshot: current arena, step counter, statistics rings
+  const size_t series_bytes = sizeof(double) * kSeriesStride * E->cap * E->n;
+  void *saved = nullptr, *saved_series = nullptr;
+  if (hipMalloc(&saved, E->arena_bytes) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", E->arena_bytes);
+  if (hipMalloc(&saved_series, series_bytes) != hipSuccess) {
+    (void)hipFree(saved);
+    return fail(CMF_ENOMEM, "hipMalloc of the statistics snapshot failed");
+  }
+  const int parity0 = E->parity, spt9_0 = E->spt9, spt3d_0 = E->spt3d;
+  int64_t step0 = 0;
+  hipError_t e = hipMemcpyAsync(saved, E->arena[parity0], E->arena_bytes, hipMemcpyDeviceToDevice, E->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(saved_series, E->series, series_bytes, hipMemcpyDeviceToDevice, E->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&step0, E->step_dev, sizeof(int64_t), hipMemcpyDeviceToHost, E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(saved);
+    (void)hipFree(saved_series);
+    return fail(CMF_EHIP, "ensemble autotune snapshot failed: %s", hipGetErrorString(e));
+  }
+  std::vector<cmf_ensemble_tiles> done;
+  int rc = CMF_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(CMF_EHIP, "hipEventCreate failed");
+  for (int a : c9) {
+    for (int b : c3) {
+      if (rc != CMF_OK) break;
+      rc = ens_build_tiles(E, a, b);
+      if (rc != CMF_OK) break;
+      rc = ens_enqueue_step(E);  // untimed
+      hipError_t x = hipSuccess;
+      if (rc == CMF_OK) x = hipEventRecord(e0, E->stream);
+      for (int k = 0; k < steps_per_trial && rc == CMF_OK && x == hipSuccess; ++k) rc = ens_enqueue_step(E);
+      if (rc == CMF_OK && x == hipSuccess) x = hipEventRecord(e1, E->stream);
+      if (rc == CMF_OK && x == hipSuccess) x = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (rc == CMF_OK && x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+      if (rc == CMF_OK && x != hipSuccess) rc = fail(CMF_EHIP, "ensemble autotune timing failed: %s", hipGetErrorString(x));
+      if (rc == CMF_OK) done.push_back(cmf_ensemble_tiles{a, b, (double)ms / steps_per_trial});
+    }
+    if (rc != CMF_OK) break;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // restore the state exactly
+  (void)hipStreamSynchronize(E->stream);
+  E->parity = parity0;
+  e = hipMemcpyAsync(E->arena[parity0], saved, E->arena_bytes, hipMemcpyDeviceToDevice, E->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->series, saved_series, series_bytes, hipMemcpyDeviceToDevice, E->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->step_dev, &step0, sizeof(int64_t), hipMemcpyHostToDevice, E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  (void)hipFree(saved);
+  (void)hipFree(saved_series);
+  if (rc == CMF_OK && e != hipSuccess) rc = fail(CMF_EHIP, "ensemble autotune restore failed: %s", hipGetErrorString(e));
+  if (rc != CMF_OK || done.empty()) {
+    const std::string msg = rc != CMF_OK ? g_last_error : std::string("no trial ran");
+    (void)ens_build_tiles(E, spt9_0, spt3d_0);
+    return fail(rc != CMF_OK ? rc : CMF_EHIP, "%s", msg.c_str());
+  }
+  size_t best = 0;
+  for (size_t k = 1; k < done.size(); ++k)
+    if (done[k].ms_per_step < done[best].ms_per_step) best = k;
+  rc = ens_build_tiles(E, done[best].spt9, done[best].spt3d);
+  if (rc != CMF_OK) return rc;
+  if (trials)
+    for (size_t k = 0; k < done.size() && (int32_t)k < cap; ++k) trials[k] = done[k];
+  if (n_out) *n_out = (int32_t)done.size();
   return CMF_OK;
 }
 

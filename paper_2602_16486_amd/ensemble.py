@@ -81,6 +81,27 @@ class Ensemble:
     def step(self, n=1):
         _lib.check(self._lib.cmf_ensemble_step(self._h, int(n)))
 
+    # -- tile shape ---------------------------------------------------------
+    @property
+    def tiles(self):
+        """(spt9, spt3d): sites per thread of the D2Q9 and of the 3-D tiles."""
+        out = _lib.EnsembleTiles()
+        _lib.check(self._lib.cmf_ensemble_get_tiles(self._h, ctypes.byref(out)))
+        return out.spt9, out.spt3d
+
+    def set_tiles(self, spt9, spt3d):
+        _lib.check(self._lib.cmf_ensemble_set_tiles(self._h, int(spt9), int(spt3d)))
+
+    def autotune(self, steps_per_trial=5):
+        """Time the candidate tile shapes (state restored afterwards), keep
+        the fastest; returns a list of (spt9, spt3d, ms_per_step)."""
+        cap = 64
+        buf = (_lib.EnsembleTiles * cap)()
+        n = ctypes.c_int32()
+        _lib.check(self._lib.cmf_ensemble_autotune(self._h, int(steps_per_trial), buf, cap,
+                                                   ctypes.byref(n)))
+        return [(buf[k].spt9, buf[k].spt3d, buf[k].ms_per_step) for k in range(min(n.value, cap))]
+
     def profile_steps(self, n):
         ms = ctypes.c_double()
         _lib.check(self._lib.cmf_ensemble_profile_steps(self._h, int(n), ctypes.byref(ms)))

@@ -155,8 +155,13 @@ def ensemble_summary(outdir):
         f"Workload: {e['replicas']} replicas, {e['sites']} sites, {alg} algorithmic bytes per step "
         "(2 Q 4 B per site, summed over the replicas).",
         "",
+        f"Tile shape: {e['tiles_sites_per_thread']['d2q9']} (D2Q9) and {e['tiles_sites_per_thread']['3d']} (3-D) "
+        "sites per thread, the shape `python bench.py` tuned, passed through the environment.",
+        "",
         "Command (repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`):",
         "",
+        f"    export CMF_ENSEMBLE_SPT9={e['tiles_sites_per_thread']['d2q9']} "
+        f"CMF_ENSEMBLE_SPT27={e['tiles_sites_per_thread']['3d']}",
         "    " + CMD_ENS,
         "    python profile_summary.py gpurun_out",
         "",

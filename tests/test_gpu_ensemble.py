@@ -139,3 +139,61 @@ def test_invalid_ensembles_are_rejected():
         Ensemble([])
     with pytest.raises(_lib.CmfError):
         Ensemble([{"q": 9, "shape": (8, 8, 2)}])
+
+
+def test_set_tiles_mid_run_keeps_results():
+    """Changing the tile shape between steps (cmf_ensemble_set_tiles) leaves
+    every population bit-identical to an untouched ensemble."""
+    states = [_state(r, 500 + k) for k, r in enumerate(REPLICAS)]
+    out = []
+    for retile in (False, True):
+        with Ensemble(REPLICAS, storage="f32") as ens:
+            for k, f in enumerate(states):
+                ens.set_populations(k, f)
+            ens.step(5)
+            if retile:
+                tiles0 = ens.info["tiles"]
+                ens.set_tiles(5, 3)
+                assert ens.tiles == (5, 3)
+                assert ens.info["tiles"] != tiles0
+            ens.step(37)  # one captured graph, re-captured for the new tiles
+            out.append([ens.get_populations(k) for k in range(len(REPLICAS))])
+    for k in range(len(REPLICAS)):
+        assert np.array_equal(out[0][k], out[1][k]), f"replica {k}"
+
+
+def test_autotune_restores_state_and_keeps_results():
+    states = [_state(r, 600 + k) for k, r in enumerate(REPLICAS)]
+    with Ensemble(REPLICAS, storage="f32") as ens:
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(3)
+        before = [ens.get_populations(k) for k in range(len(REPLICAS))]
+        trials = ens.autotune(steps_per_trial=2)
+        # D2Q9 and 3-D replicas present: 6 x 4 shapes
+        assert len(trials) == 24 and all(t[2] > 0 for t in trials)
+        best = min(trials, key=lambda t: t[2])
+        assert ens.tiles == best[:2]
+        assert ens.step_index == 3
+        for k in range(len(REPLICAS)):
+            assert np.array_equal(ens.get_populations(k), before[k])
+        ens.step(6)
+        got = [ens.get_populations(k) for k in range(len(REPLICAS))]
+        st = [ens.stats(k) for k in range(len(REPLICAS))]
+    with Ensemble(REPLICAS, storage="f32", flags=_lib.FLAG_NO_GRAPH) as ref:
+        for k, f in enumerate(states):
+            ref.set_populations(k, f)
+        ref.step(9)
+        for k in range(len(REPLICAS)):
+            assert np.array_equal(got[k], ref.get_populations(k)), f"replica {k}"
+            ref_st = ref.stats(k)
+            assert np.array_equal(st[k][:, 0], np.arange(9))
+            assert np.allclose(st[k], ref_st, rtol=1e-12, atol=1e-18), f"replica {k} statistics"
+
+
+def test_set_tiles_rejects_bad_shapes():
+    with Ensemble(REPLICAS[:2], storage="f32") as ens:
+        for bad in ((0, 1), (1, 0), (17, 1), (1, 17)):
+            with pytest.raises(Exception):
+                ens.set_tiles(*bad)
+        assert ens.tiles == (3, 1)
