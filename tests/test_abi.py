@@ -69,6 +69,9 @@ def test_null_arguments_are_rejected():
     assert lib.cmf_step(None, 1) == _lib.CMF_EINVAL
     assert lib.cmf_destroy(None) == _lib.CMF_EINVAL
     assert lib.cmf_noise_sample(10, 1, 0, 0, 0, 4, 0, None) == _lib.CMF_EINVAL
+    assert lib.cmf_ensemble_get_tiles(None, None) == _lib.CMF_EINVAL
+    assert lib.cmf_ensemble_set_tiles(None, 3, 1) == _lib.CMF_EINVAL
+    assert lib.cmf_ensemble_autotune(None, 2, None, 0, None) == _lib.CMF_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):
