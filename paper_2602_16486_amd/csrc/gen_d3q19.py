@@ -18,9 +18,11 @@ Evaluation order, chosen for few operations:
 * every basis polynomial has a definite parity in each coordinate, so both
   r = M d and d = M^-1 r go through the sign classes of each orbit of
   velocities with equal |c_a| (a butterfly of sums and differences);
-* N(u)^-1 is applied as a polynomial matrix in u.  Its columns 1-3 are
-  dropped: the central first moments k_1..k_3 vanish identically (before
-  and after the collision), and callers pass them as zero.
+* N(u)^-1 is applied row by row in the combinations D = 3 u_x^2 - |u|^2,
+  E = u_y^2 - u_z^2 and the products u_a k_b that the rows share.  Its
+  columns 1-3 are dropped: the central first moments k_1..k_3 vanish
+  identically (before and after the collision), and callers pass them as
+  zero.
 
 Every emitted function is checked here symbolically against its definition.
 
@@ -198,100 +200,137 @@ def gen_raw_moments(L, d):
     return lines + emit(exprs, [f"r[{v}]" for v in range(19)], "a")
 
 
-def reduced_form(e, u):
-    """The cheapest of a few equivalent forms of a polynomial entry of
-    N(u)^-1, written in u_a and the squares uxx, uyy, uzz, uu = |u|^2."""
-    ux, uy, uz = u
-    A, B, C, U2 = sp.symbols("uxx uyy uzz uu")
-    q = 0
-    for (i, j, k), coef in sp.Poly(sp.expand(e), ux, uy, uz).terms():
-        q += coef * A ** (i // 2) * B ** (j // 2) * C ** (k // 2) * ux ** (i % 2) * uy ** (j % 2) * uz ** (k % 2)
-    cands = [sp.expand(e), q, sp.factor(q)]
-    for var, rest in ((A, B + C), (B, A + C), (C, A + B)):
-        s = sp.expand(q.subs(var, U2 - rest))
-        cands += [s, sp.factor(s)]
-    if q.free_symbols:
-        cands.append(sp.horner(q))
-    return min(cands, key=sp.count_ops)
+class Steps:
+    """Straight-line code as named temporaries: define() records each one
+    with its expression in earlier temporaries, expand() writes any
+    expression back in the inputs (for the symbolic checks)."""
+
+    def __init__(self):
+        self.defs, self.value = [], {}
+
+    def define(self, name, expr):
+        sym = sp.Symbol(name)
+        self.defs.append((sym, expr))
+        self.value[sym] = sp.expand(sp.sympify(expr).subs(self.value))
+        return sym
+
+    def expand(self, expr):
+        return sp.expand(sp.sympify(expr).subs(self.value))
+
+    def lines(self):
+        return [f"  const R {sym} = {_PRINT.doprint(e)};" for sym, e in self.defs]
 
 
 def gen_shift_inverse(L, k):
-    """r = N(u)^-1 k for k_1 = k_2 = k_3 = 0."""
+    """r = N(u)^-1 k for k_1 = k_2 = k_3 = 0, written with the second
+    central moments' combinations D = 3 u_x^2 - |u|^2 and E = u_y^2 - u_z^2
+    and the products u_a k_7..k_9 shared between the rows; checked against
+    the entries of N(u)^-1 (computed above by forward substitution)."""
     ux, uy, uz = L.u
-    A, B, C, U2 = sp.symbols("uxx uyy uzz uu")
-    exprs = []
-    for v in range(19):
-        e = 0 if v in (1, 2, 3) else k[v]
-        for c in range(19):
-            if c == v or c in (1, 2, 3) or L.Ninv[v, c] == 0:
-                continue
-            e += reduced_form(L.Ninv[v, c], L.u) * k[c]
-        exprs.append(e)
-    back = {A: ux ** 2, B: uy ** 2, C: uz ** 2, U2: ux ** 2 + uy ** 2 + uz ** 2}
+    R = sp.Rational
+    S = Steps()
+    rho = k[0]
+    uxx, uyy, uzz = S.define("uxx", ux * ux), S.define("uyy", uy * uy), S.define("uzz", uz * uz)
+    uu = S.define("uu", uxx + uyy + uzz)
+    D = S.define("dd", 3 * uxx - uu)
+    E = S.define("ee", uyy - uzz)
+    r = [None] * 19
+    r[0] = rho
+    r[1], r[2], r[3] = S.define("jx", rho * ux), S.define("jy", rho * uy), S.define("jz", rho * uz)
+    y7, x7 = S.define("y7", uy * k[7]), S.define("x7", ux * k[7])
+    z8, y8 = S.define("z8", uz * k[8]), S.define("y8", uy * k[8])
+    z9, x9 = S.define("z9", uz * k[9]), S.define("x9", ux * k[9])
+    r[4] = S.define("t4", k[4] + rho * uu)
+    r[5] = S.define("t5", k[5] + rho * D)
+    r[6] = S.define("t6", k[6] + rho * E)
+    r[7] = S.define("t7", k[7] + r[1] * uy)
+    r[8] = S.define("t8", k[8] + r[2] * uz)
+    r[9] = S.define("t9", k[9] + r[1] * uz)
+    A = S.define("aa", 3 * rho * uu + 5 * k[4])
+    F = S.define("ff", A - k[5])
+    s79, s78, s89 = S.define("s79", y7 + z9), S.define("s78", x7 + z8), S.define("s89", y8 + x9)
+    d79, d87, d98 = S.define("d79", y7 - z9), S.define("d87", z8 - x7), S.define("d98", x9 - y8)
+    h56p, h56m = S.define("h56p", r[5] + r[6]), S.define("h56m", r[5] - r[6])
+    r[10] = S.define("t10", k[10] + ux * (A + 2 * k[5]) + 6 * s79)
+    r[11] = S.define("t11", k[11] + uy * (F + 3 * k[6]) + 6 * s78)
+    r[12] = S.define("t12", k[12] + uz * (F - 3 * k[6]) + 6 * s89)
+    r[13] = S.define("t13", k[13] + ux * r[6] + 2 * d79)
+    r[14] = S.define("t14", k[14] - R(1, 2) * uy * h56p + 2 * d87)
+    r[15] = S.define("t15", k[15] + R(1, 2) * uz * h56m + 2 * d98)
+    c1 = S.define("c1", ux * k[10] + uy * k[11] + uz * k[12])
+    c2 = S.define("c2", ux * s79 + uy * z8)
+    c3 = S.define("c3", uy * k[11] + uz * k[12])
+    c4 = S.define("c4", uy * k[11] - uz * k[12])
+    c5 = S.define("c5", uy * k[14] - uz * k[15])
+    c6 = S.define("c6", uy * k[14] + uz * k[15])
+    r[16] = S.define("t16", k[16] + 4 * c1 + 24 * c2 + uu * (rho * (3 * uu + 4) + 10 * k[4])
+                     + 2 * D * k[5] + 6 * E * k[6])
+    r[17] = S.define("t17", k[17] + D * (rho * (R(5, 3) - 3 * uxx - uu) - R(4, 3) * k[4])
+                     + E * (3 * rho * E + 5 * k[6]) - R(1, 3) * (15 * uxx - uu) * k[5]
+                     + 8 * ux * s79 - 16 * uy * z8 + R(4, 3) * ux * k[10] - R(2, 3) * c3 - 6 * c5)
+    r[18] = S.define("t18", k[18] + E * (rho * (6 * uxx - 4 * uu + R(5, 3)) - R(4, 3) * k[4] + R(5, 3) * k[5])
+                     + (5 * uxx - 3 * uu) * k[6] + 8 * ux * d79 + R(2, 3) * c4 + 4 * ux * k[13] - 2 * c6)
     zero = {k[1]: 0, k[2]: 0, k[3]: 0}
     for v in range(19):
         ref = sum(L.Ninv[v, c] * k[c] for c in range(19)).subs(zero)
-        assert sp.expand(exprs[v].subs(back) - ref) == 0
-    lines = ["  const R uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;",
-             "  const R uu = uxx + uyy + uzz;"]
-    lines += emit(exprs, [f"const R t{v}" for v in range(19)], "q")
-    lines += [f"  k[{v}] = t{v};" for v in range(19)]
-    return lines
+        assert sp.expand(S.expand(r[v]) - ref) == 0, v
+    return S.lines() + [f"  k[{v}] = {_PRINT.doprint(r[v])};" for v in range(1, 19)]
 
 
 def gen_populations(L, r, d):
-    """d_i = w_i sum_v P_v(c_i) r_v / b_v: per orbit, one sum per sign class,
-    then the inverse butterfly over the orbit's members."""
-    exprs, names, gval = [], [], {}
-    for absc in L.orbits:
-        w = W[L.orbits[absc][0]]
-        nz = [a for a in range(3) if absc[a]]
-        for n in range(len(nz) + 1):
-            for axes in itertools.combinations(nz, n):
-                cls = axis_class(*axes)
-                e = 0
-                for v in range(19):
-                    if L.parity[v] == cls:
-                        e += w * L.P_abs(v, absc) / L.b[v] * r[v]
-                name = f"g{orbit_tag(absc)}_{class_tag(cls)}"
-                exprs.append(sp.expand(e))
-                names.append(f"const R {name}")
-                gval[(absc, cls)] = sp.expand(e)
-    lines = emit(exprs, names, "p")
-    out = {}
-    for absc in L.orbits:
-        nz = [a for a in range(3) if absc[a]]
-        t = orbit_tag(absc)
-        g = lambda cls: f"g{t}_{class_tag(cls)}"
-        if not nz:
-            i = L.orbits[absc][0]
-            lines.append(f"  d[{i}] = {g((0, 0, 0))};")
-            out[i] = gval[(absc, (0, 0, 0))]
-        elif len(nz) == 1:
-            ca = axis_class(nz[0])
-            p, m = L.member(absc, [1]), L.member(absc, [-1])
-            lines += [f"  d[{p}] = {g((0, 0, 0))} + {g(ca)};", f"  d[{m}] = {g((0, 0, 0))} - {g(ca)};"]
-            out[p] = gval[(absc, (0, 0, 0))] + gval[(absc, ca)]
-            out[m] = gval[(absc, (0, 0, 0))] - gval[(absc, ca)]
-        else:
-            a, b = nz
-            ca, cb, cab = axis_class(a), axis_class(b), axis_class(a, b)
-            pp, mm = L.member(absc, [1, 1]), L.member(absc, [-1, -1])
-            pm, mp = L.member(absc, [1, -1]), L.member(absc, [-1, 1])
-            lines += [f"  const R e1_{t} = {g((0, 0, 0))} + {g(cab)};",
-                      f"  const R e2_{t} = {g((0, 0, 0))} - {g(cab)};",
-                      f"  const R o1_{t} = {g(ca)} + {g(cb)};",
-                      f"  const R o2_{t} = {g(ca)} - {g(cb)};",
-                      f"  d[{pp}] = e1_{t} + o1_{t};", f"  d[{mm}] = e1_{t} - o1_{t};",
-                      f"  d[{pm}] = e2_{t} + o2_{t};", f"  d[{mp}] = e2_{t} - o2_{t};"]
-            G = lambda cls: gval[(absc, cls)]
-            out[pp] = G((0, 0, 0)) + G(cab) + G(ca) + G(cb)
-            out[mm] = G((0, 0, 0)) + G(cab) - G(ca) - G(cb)
-            out[pm] = G((0, 0, 0)) - G(cab) + G(ca) - G(cb)
-            out[mp] = G((0, 0, 0)) - G(cab) - G(ca) + G(cb)
+    """d_i = w_i sum_v P_v(c_i) r_v / b_v.  Every P_v is even or odd in
+    each coordinate, so each orbit of equal |c_a| needs one sum per sign
+    class and a butterfly over its members; the three axis orbits and the
+    three face-diagonal orbits also share the parts of those sums that the
+    permutations of the axes leave alike.  Checked against W M^T B^-1."""
+    S = Steps()
+    w0, w1, w2 = W[0], W[1], W[7]
+    b = L.b
+
+    def a(v, w):  # w r_v / b_v
+        return (w / b[v]) * r[v]
+
+    out = [None] * 19
+    out[0] = S.define("p0", a(0, w0) - a(4, w0) + a(16, w0))
+    # axis orbits, |c|^2 = 1: even parts C + 2P, C - P + Q, C - P - Q
+    C = S.define("pc", a(0, w1) - 2 * a(16, w1))
+    P = S.define("pp", a(5, w1) - a(17, w1))
+    Q = S.define("pq", a(6, w1) - a(18, w1))
+    CP = S.define("pcp", C - P)
+    even = [S.define("pex", C + 2 * P), S.define("pey", CP + Q), S.define("pez", CP - Q)]
+    odd = [S.define(f"po{n}", a(1 + ax, w1) - 2 * a(10 + ax, w1)) for ax, n in enumerate("xyz")]
+    for ax in range(3):
+        cp, cm = [0, 0, 0], [0, 0, 0]
+        cp[ax], cm[ax] = 1, -1
+        out[L.C.index(tuple(cp))] = even[ax] + odd[ax]
+        out[L.C.index(tuple(cm))] = even[ax] - odd[ax]
+    # face-diagonal orbits, |c|^2 = 2
+    C2 = S.define("fc", a(0, w2) + a(4, w2) + a(16, w2))
+    P2 = S.define("fp", a(5, w2) + a(17, w2))
+    Q2 = S.define("fq", a(6, w2) + a(18, w2))
+    CP2 = S.define("fcp", C2 + P2)
+    E2 = {(0, 1): S.define("fe110", CP2 + Q2), (0, 2): S.define("fe101", CP2 - Q2),
+          (1, 2): S.define("fe011", C2 - 2 * P2)}
+    X1 = [S.define(f"f{n}", a(1 + ax, w2) + a(10 + ax, w2)) for ax, n in enumerate("xyz")]
+    A3 = [S.define(f"f{13 + ax}", a(13 + ax, w2)) for ax in range(3)]
+    OO = {(0, 1): S.define("fxy", a(7, w2)), (0, 2): S.define("fxz", a(9, w2)),
+          (1, 2): S.define("fyz", a(8, w2))}
+    # class odd in axis a only: X1[a] +- (the mode 13 + a with its sign here)
+    OA = {(0, 1): (S.define("fx110", X1[0] + A3[0]), S.define("fy110", X1[1] - A3[1])),
+          (0, 2): (S.define("fx101", X1[0] - A3[0]), S.define("fz101", X1[2] + A3[2])),
+          (1, 2): (S.define("fy011", X1[1] + A3[1]), S.define("fz011", X1[2] - A3[2]))}
+    for (ax, bx), (oa, ob) in OA.items():
+        t = f"{ax}{bx}"
+        e1, e2 = S.define(f"e1_{t}", E2[(ax, bx)] + OO[(ax, bx)]), S.define(f"e2_{t}", E2[(ax, bx)] - OO[(ax, bx)])
+        o1, o2 = S.define(f"o1_{t}", oa + ob), S.define(f"o2_{t}", oa - ob)
+        for sa in (1, -1):
+            for sb in (1, -1):
+                c = [0, 0, 0]
+                c[ax], c[bx] = sa, sb
+                out[L.C.index(tuple(c))] = (e1 + sa * o1) if sa == sb else (e2 + sa * o2)
     for i in range(19):
-        assert sp.expand(out[i] - sum(L.Minv[i, v] * r[v] for v in range(19))) == 0
-    return lines
+        assert sp.expand(S.expand(out[i]) - sum(L.Minv[i, v] * r[v] for v in range(19))) == 0, i
+    return S.lines() + [f"  d[{i}] = {_PRINT.doprint(out[i])};" for i in range(19)]
 
 
 def main():
