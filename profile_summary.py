@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Summarise the rocprofv3 runs of bench.py into profiles/.
 
-Inputs (written by rocprofv3 under a results directory):
+Inputs (written by rocprofv3 under a results directory, `out/` in the
+commands below; any directory works):
   <dir>/prof_trace/trace_kernel_stats.csv        (--kernel-trace --stats)
   <dir>/prof_fetch/fetch_counter_collection.csv  (--pmc FETCH_SIZE)
   <dir>/prof_write/write_counter_collection.csv  (--pmc WRITE_SIZE)
@@ -15,7 +16,7 @@ Outputs: profiles/k_step_d3q27_f32_256cube.md (the summary) and
 profiles/k_step_d3q27_f32_256cube.counters.json (read by bench.py, tied to
 the kernel sources' hash and the launch shape).
 
-    python profile_summary.py gpurun_out
+    python profile_summary.py out
 """
 import csv
 import json
@@ -33,9 +34,9 @@ N = 256 ** 3
 ALG_BYTES = 2 * 27 * 4 * N
 COPY_BYTES = 27 * N * 4  # per direction
 
-CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv "
+CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d out/prof_trace -o trace --output-format csv "
              "-- python3 bench.py --steps 400 --warmup 64 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
-CMD_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv "
+CMD_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d out/prof_fetch -o fetch --output-format csv "
              "-- python3 bench.py --steps 10 --warmup 32 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
 CMD_WRITE = CMD_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("prof_fetch", "prof_write").replace(
     "-o fetch", "-o write")
@@ -86,14 +87,14 @@ def main(outdir):
         "",
         "Workload: " + bench_line["config"]["workload"] + f"; launch (block, grid) = {tuple(launch)}.",
         "",
-        "Commands (run from the repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`;",
-        "the three runs share one tuning cache, `CMFLB_TUNE_CACHE=gpurun_out/tune.txt`, written by a",
+        "Commands (run from the repository root on a machine with an MI355X, after `cd /tmp && export TMPDIR=/tmp`;",
+        "the three runs share one tuning cache, `CMFLB_TUNE_CACHE=out/tune.txt`, written by a",
         "preceding `python bench.py`):",
         "",
         "    " + CMD_TRACE,
         "    " + CMD_FETCH,
         "    " + CMD_WRITE,
-        "    python profile_summary.py gpurun_out",
+        "    python profile_summary.py out",
         "",
         "## Kernel trace (--kernel-trace --stats)",
         "",
@@ -130,7 +131,7 @@ def main(outdir):
 
 
 ENS_KERNEL = "void cmf::k_ensemble_step<float, float, false, false>"
-CMD_ENS = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_ens -o ens --output-format csv "
+CMD_ENS = ("rocprofv3 --kernel-trace --stats -d out/prof_ens -o ens --output-format csv "
            "-- python3 bench.py --steps 50 --warmup 16 --variants \"\" --d3q19 \"\" --no-cpu --no-tune")
 
 
@@ -158,12 +159,12 @@ def ensemble_summary(outdir):
         f"Tile shape: {e['tiles_sites_per_thread']['d2q9']} (D2Q9) and {e['tiles_sites_per_thread']['3d']} (3-D) "
         "sites per thread, the shape `python bench.py` tuned, passed through the environment.",
         "",
-        "Command (repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`):",
+        "Command (repository root on a machine with an MI355X, after `cd /tmp && export TMPDIR=/tmp`):",
         "",
         f"    export CMF_ENSEMBLE_SPT9={e['tiles_sites_per_thread']['d2q9']} "
         f"CMF_ENSEMBLE_SPT27={e['tiles_sites_per_thread']['3d']}",
         "    " + CMD_ENS,
-        "    python profile_summary.py gpurun_out",
+        "    python profile_summary.py out",
         "",
         "| kernel | calls | average ns | min ns | max ns |",
         "|---|---|---|---|---|",
@@ -183,7 +184,7 @@ def ensemble_summary(outdir):
     print("\n".join(lines))
 
 
-CMD_VAR = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_var -o var --output-format csv "
+CMD_VAR = ("rocprofv3 --kernel-trace --stats -d out/prof_var -o var --output-format csv "
            "-- python3 bench.py --steps 100 --warmup 32 --no-cpu --no-tune --no-ensemble")
 VARIANTS = [  # (kernel name prefix, label, q, bytes per stored value, bench.py entry)
     ("void cmf::k_step<cmf::D3Q27, float, float, false, true, false>", "D3Q27 FP32", 27, 4, None),
@@ -210,10 +211,10 @@ def variants_summary(outdir):
         "Workload: 256^3 periodic, rest start, rho0=1, tau=0.8, kT=1e-4, Philox seed 1, the paper's rates; "
         "launch shapes from the tuning cache of a preceding `python bench.py` (`CMFLB_TUNE_CACHE`).",
         "",
-        "Command (repository root on the GPU host, after `cd /tmp && export TMPDIR=/tmp`):",
+        "Command (repository root on a machine with an MI355X, after `cd /tmp && export TMPDIR=/tmp`):",
         "",
         "    " + CMD_VAR,
-        "    python profile_summary.py gpurun_out",
+        "    python profile_summary.py out",
         "",
         "| kernel | dispatches | average ms | median ms | bench.py live ms | algorithmic B/site | GB/s (median) | of 8 TB/s |",
         "|---|---|---|---|---|---|---|---|",
@@ -246,6 +247,6 @@ def variants_summary(outdir):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")
-    ensemble_summary(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")
-    variants_summary(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out")
+    main(sys.argv[1] if len(sys.argv) > 1 else "out")
+    ensemble_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
+    variants_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
