@@ -197,3 +197,18 @@ def test_set_tiles_rejects_bad_shapes():
             with pytest.raises(Exception):
                 ens.set_tiles(*bad)
         assert ens.tiles == (3, 1)
+
+
+def test_autotune_without_statistics():
+    """CMF_FLAG_NO_STATS ensembles tune too and keep their state."""
+    states = [_state(r, 700 + k) for k, r in enumerate(REPLICAS)]
+    with Ensemble(REPLICAS, storage="f32", flags=_lib.FLAG_NO_STATS) as ens:
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(2)
+        before = [ens.get_populations(k) for k in range(len(REPLICAS))]
+        trials = ens.autotune(steps_per_trial=1)
+        assert len(trials) == 24
+        assert ens.step_index == 2
+        for k in range(len(REPLICAS)):
+            assert np.array_equal(ens.get_populations(k), before[k])
