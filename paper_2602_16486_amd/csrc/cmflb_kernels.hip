@@ -467,7 +467,9 @@ __device__ __forceinline__ const T *at_byte(const T *base, uint32_t boff) {
 // whole offset inside the buffer is one 32-bit byte count from the uniform
 // buffer base (the buffer is below 4 GiB, checked at creation), which saves
 // the per-lane 64-bit address arithmetic.
-template <class L, typename S, typename R, bool LANE_ROWS>
+// NT_C0: non-temporal loads for the populations with c_x = 0 (uniform
+// rows whose lines are whole cache lines only).
+template <class L, typename S, typename R, bool LANE_ROWS, bool NT_C0 = false>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
                                           const float *scale, int nx, int ny,
                                           int nz, int x, int y, int z) {
@@ -487,7 +489,12 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
-      d[i] = ST::load(base + xs[L::cx[i] + 1], scale[weight_class<L>(i)]);
+      const float sc = scale[weight_class<L>(i)];
+      // (the condition is a compile-time constant once the loop is unrolled)
+      if (NT_C0 && L::cx[i] == 0)
+        d[i] = ST::template load<true>(base + xs[1], sc);
+      else
+        d[i] = ST::template load<false>(base + xs[L::cx[i] + 1], sc);
     }
   } else {
     constexpr uint32_t B = sizeof(S);
@@ -561,7 +568,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
     const TileXY c = tile_coords(tile, p.nxb, ny, BX);
     if (c.x < nx) {
       R d[Q];
-      load_site<L, S, R, false>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+      load_site<L, S, R, false, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, (uint32_t)site, step, acc);
