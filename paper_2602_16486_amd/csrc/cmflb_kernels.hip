@@ -467,8 +467,10 @@ __device__ __forceinline__ const T *at_byte(const T *base, uint32_t boff) {
 // whole offset inside the buffer is one 32-bit byte count from the uniform
 // buffer base (the buffer is below 4 GiB, checked at creation), which saves
 // the per-lane 64-bit address arithmetic.
-// NT_C0: non-temporal loads for the populations with c_x = 0 (uniform
-// rows whose lines are whole cache lines only).
+// NT_C0: non-temporal loads for the populations with c_x = 0, only when
+// every population row is a whole number of cache lines (then tiles, which
+// start at multiples of 256 sites of a replica or row, never share a line
+// of such a row).
 template <class L, typename S, typename R, bool LANE_ROWS, bool NT_C0 = false>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
                                           const float *scale, int nx, int ny,
@@ -511,7 +513,11 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const uint32_t e = sblk[L::cy[i] + 1][L::cz[i] + 1] + (uint32_t)i * unx + xs[L::cx[i] + 1];
-      d[i] = ST::load(at_byte(src, e * B), scale[weight_class<L>(i)]);
+      const float sc = scale[weight_class<L>(i)];
+      if (NT_C0 && L::cx[i] == 0)
+        d[i] = ST::template load<true>(at_byte(src, e * B), sc);
+      else
+        d[i] = ST::template load<false>(at_byte(src, e * B), sc);
     }
   }
 }
@@ -1069,7 +1075,7 @@ __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
   const int y = (int)(row % ny);
   const int z = (int)(row / ny);
   R d[L::Q];
-  load_site<L, S, R, true>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
+  load_site<L, S, R, true, NT>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
   collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);
   store_site<L, S, R, true, NT>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
 }

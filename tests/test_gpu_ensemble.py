@@ -212,3 +212,29 @@ def test_autotune_without_statistics():
         assert ens.step_index == 2
         for k in range(len(REPLICAS)):
             assert np.array_equal(ens.get_populations(k), before[k])
+
+
+ALIGNED = [  # every population row a whole number of 128-byte lines in FP32 and FP16
+    {"q": 9, "shape": (64, 40), "kT": 1e-4, "tau": 0.7, "seed": 21, "replica": 0},
+    {"q": 27, "shape": (64, 9, 7), "kT": 3e-4, "tau": 0.55, "seed": 22, "replica": 1},
+    {"q": 19, "shape": (128, 5, 6), "kT": 2e-4, "tau": 0.65, "seed": 23, "replica": 2},
+    {"q": 9, "shape": (192, 3), "kT": 0.0, "tau": 0.8, "seed": 24, "replica": 3},
+]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_aligned_replicas_match_standalone_lattices(storage):
+    """Ensembles whose rows are all whole cache lines take the non-temporal
+    store and c_x = 0 load path; replicas still equal standalone lattices."""
+    states = [_state(r, 800 + k) for k, r in enumerate(ALIGNED)]
+    with Ensemble(ALIGNED, storage=storage) as ens:
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(35)
+        got = [ens.get_populations(k) for k in range(len(ALIGNED))]
+    for k, r in enumerate(ALIGNED):
+        kw = {key: r[key] for key in ("kT", "tau", "seed", "replica")}
+        with Lattice(r["q"], r["shape"], storage=storage, **kw) as lat:
+            lat.set_populations(states[k])
+            lat.step(35)
+            assert np.array_equal(got[k], lat.get_populations()), f"replica {k}"
