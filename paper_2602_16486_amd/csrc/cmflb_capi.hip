@@ -1385,30 +1385,40 @@ void *ens_replica_buffer(cmf_ensemble *E, int index) {
 // must be idle.
 int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
   std::vector<int32_t> tile_rep;
+  std::vector<int> tile0(E->n), ntl(E->n), spt(E->n);
   for (int pass = 0; pass < 2; ++pass)
     for (int r = 0; r < E->n; ++r) {
       const int q = E->reps[r].desc.q;
       if ((pass == 0) != (q != 9)) continue;
-      cmf_ensemble::Rep &rp = E->reps[r];
-      rp.tile0 = (int)tile_rep.size();
-      rp.spt = q == 9 ? spt9 : spt3d;
-      const int64_t tsites = (int64_t)rp.spt * kEnsembleBlock;
-      rp.ntiles = (int)((rp.N + tsites - 1) / tsites);
-      if ((int64_t)tile_rep.size() + rp.ntiles >= ((int64_t)1 << 31))
+      tile0[r] = (int)tile_rep.size();
+      spt[r] = q == 9 ? spt9 : spt3d;
+      const int64_t tsites = (int64_t)spt[r] * kEnsembleBlock;
+      const int64_t n = (E->reps[r].N + tsites - 1) / tsites;
+      if ((int64_t)tile_rep.size() + n >= ((int64_t)1 << 31))
         return fail(CMF_EINVAL, "ensemble has too many tiles");
-      tile_rep.insert(tile_rep.end(), rp.ntiles, r);
+      ntl[r] = (int)n;
+      tile_rep.insert(tile_rep.end(), ntl[r], r);
     }
   const int nt = (int)tile_rep.size();
   if (nt > E->tiles_cap) {
+    // allocate first, so that a failure leaves the current tiling usable
+    int32_t *map = nullptr;
+    double *parts = nullptr;
+    if (hipMalloc((void **)&map, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc((void **)&parts, 2 * sizeof(double) * kPartStride * nt) != hipSuccess) {
+      if (map) (void)hipFree(map);
+      return fail(CMF_ENOMEM, "allocation of the tile map (%d tiles) failed", nt);
+    }
     if (E->d_tile_rep) (void)hipFree(E->d_tile_rep);
     if (E->partials) (void)hipFree(E->partials);
-    E->d_tile_rep = nullptr;
-    E->partials = nullptr;
-    E->tiles_cap = 0;
-    if (hipMalloc((void **)&E->d_tile_rep, sizeof(int32_t) * nt) != hipSuccess ||
-        hipMalloc((void **)&E->partials, 2 * sizeof(double) * kPartStride * nt) != hipSuccess)
-      return fail(CMF_ENOMEM, "allocation of the tile map (%d tiles) failed", nt);
+    E->d_tile_rep = map;
+    E->partials = parts;
     E->tiles_cap = nt;
+  }
+  for (int r = 0; r < E->n; ++r) {
+    E->reps[r].tile0 = tile0[r];
+    E->reps[r].ntiles = ntl[r];
+    E->reps[r].spt = spt[r];
   }
   E->ntiles = nt;
   E->spt9 = spt9;
