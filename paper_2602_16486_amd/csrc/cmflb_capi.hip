@@ -423,20 +423,29 @@ void drop_graphs(cmf_lattice *L) {
 // Apply a launch shape: step parameters, partials capacity, graphs.
 int apply_launch(cmf_lattice *L, int block, int grid, const double *amp,
                  const float *scale) {
+  // new parameters and buffers first: on failure the current shape stays
+  const int block0 = L->block;
   L->block = block;
-  fill_step_params(L, amp, scale, L->pd);
-  fill_step_params(L, amp, scale, L->pf);
-  const int nt = L->pf.ntiles;
-  L->grid = grid < nt ? grid : nt;
-  L->nparts = L->grid;
-  if (L->nparts > L->partials_cap) {
-    if (L->partials) (void)hipFree(L->partials);
-    L->partials = nullptr;
-    L->partials_cap = 0;
-    if (hipMalloc((void **)&L->partials, 2 * sizeof(double) * kPartStride * L->nparts) != hipSuccess)
+  StepParams<double> pd;
+  StepParams<float> pf;
+  fill_step_params(L, amp, scale, pd);
+  fill_step_params(L, amp, scale, pf);
+  L->block = block0;
+  const int nt = pf.ntiles;
+  const int g = grid < nt ? grid : nt;
+  if (g > L->partials_cap) {
+    double *parts = nullptr;
+    if (hipMalloc((void **)&parts, 2 * sizeof(double) * kPartStride * g) != hipSuccess)
       return fail(CMF_ENOMEM, "hipMalloc of the statistics partials failed");
-    L->partials_cap = L->nparts;
+    if (L->partials) (void)hipFree(L->partials);
+    L->partials = parts;
+    L->partials_cap = g;
   }
+  L->block = block;
+  L->pd = pd;
+  L->pf = pf;
+  L->grid = g;
+  L->nparts = g;
   drop_graphs(L);
   return CMF_OK;
 }
