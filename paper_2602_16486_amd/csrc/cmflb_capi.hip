@@ -864,21 +864,38 @@ int cmf_sk_reset(cmf_lattice *L, int32_t nbins) {
   HIP_TRY(hipStreamSynchronize(L->stream));
   const int nx = L->desc.nx, ny = L->desc.ny, nz = L->desc.nz;
   const int64_t M = (int64_t)(nx / 2 + 1) * ny * nz;
-  if (!L->sk_fields) {
+  if (!L->sk_has_plan) {
+    // all buffers and the plan, or none of them
+    auto drop = [&]() {
+      for (void **p : {(void **)&L->sk_fields, &L->sk_F, (void **)&L->sk_acc, (void **)&L->sk_perm}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+      }
+    };
+    drop();
     if (hipMalloc((void **)&L->sk_fields, sizeof(float) * 4 * L->N) != hipSuccess ||
         hipMalloc(&L->sk_F, sizeof(float) * 2 * 4 * M) != hipSuccess ||
         hipMalloc((void **)&L->sk_acc, sizeof(double) * 4 * M) != hipSuccess ||
-        hipMalloc((void **)&L->sk_perm, sizeof(int32_t) * M) != hipSuccess)
+        hipMalloc((void **)&L->sk_perm, sizeof(int32_t) * M) != hipSuccess) {
+      drop();
       return fail(CMF_ENOMEM, "structure-factor allocation failed");
+    }
     hipfftResult fr = nz > 1 ? hipfftPlan3d(&L->sk_plan, nz, ny, nx, HIPFFT_R2C)
                              : hipfftPlan2d(&L->sk_plan, ny, nx, HIPFFT_R2C);
-    if (fr != HIPFFT_SUCCESS) return fail(CMF_EHIP, "hipfft plan failed (%d)", (int)fr);
-    L->sk_has_plan = true;
-    if (hipfftSetStream(L->sk_plan, L->stream) != HIPFFT_SUCCESS)
+    if (fr != HIPFFT_SUCCESS) {
+      drop();
+      return fail(CMF_EHIP, "hipfft plan failed (%d)", (int)fr);
+    }
+    if (hipfftSetStream(L->sk_plan, L->stream) != HIPFFT_SUCCESS) {
+      (void)hipfftDestroy(L->sk_plan);
+      drop();
       return fail(CMF_EHIP, "hipfftSetStream failed");
+    }
+    L->sk_has_plan = true;
     L->sk_M = M;
   }
   if (L->sk_nbins != nbins) {
+    L->sk_nbins = 0;  // no shells until the new ones are in place
     // shell of every mode on the device, counting sort by shell on the host
     std::vector<int32_t> bin(M), perm(M);
     std::vector<int64_t> off(nbins + 1, 0);
