@@ -1,13 +1,15 @@
 // cmflb_kernels.hip -- gfx950 kernels of libcmflb: the fused pull-stream +
-// central-moment collision step (D2Q9, D3Q27), its statistics finalize, and
-// the state conversion / diagnostic kernels.
+// central-moment collision step (D2Q9, D3Q19, D3Q27; single lattices and
+// batched ensembles), its statistics reductions, and the state conversion /
+// diagnostic kernels.
 //
 // Method: De Rosis & Zhou, "A fluctuating lattice Boltzmann formulation based
-// on orthogonal central moments" (arXiv 2602.16486), Sec. 2.2 (D2Q9) and
-// Sec. 2.3 (D3Q27).  The per-site work follows the paper's "Algorithm of
-// computation": macroscopic moments (eq. macro), normals, pre-collision
-// central moments, collision (eq. cm_collision with phi of eq. phi_general),
-// back transformation f* = T(u)^-1 k*, streaming (eq. streaming).
+// on orthogonal central moments" (arXiv 2602.16486), Sec. 2.2 (D2Q9),
+// Sec. 2.3 (D3Q27) and Sec. 2.4 (D3Q19).  The per-site work follows the
+// paper's "Algorithm of computation": macroscopic moments (eq. macro),
+// normals, pre-collision central moments, collision (eq. cm_collision with
+// phi of eq. phi_general), back transformation f* = T(u)^-1 k*, streaming
+// (eq. streaming).
 //
 // Memory layout: populations are stored as deviations d_i = f_i - w_i rho0
 // in a row-interleaved structure of arrays (pop_row_offset): for lattice row
@@ -19,8 +21,9 @@
 //
 // Work decomposition: a tile is BX consecutive sites of one x-row
 // (BX = blockDim.x, a multiple of 64); a block walks tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ... and keeps its statistics in
-// registers until the end, so the partial-sum traffic is one row per block.
+// blockIdx.x, blockIdx.x + gridDim.x, ... (or has exactly one) and keeps its
+// statistics in registers until the end, so the partial-sum traffic is one
+// row per block.
 #include "cmflb_d3q19.h"
 #include "cmflb_device.h"
 #include "cmflb_internal.h"
