@@ -127,3 +127,31 @@ def test_rate_presets(q):
     assert np.array_equal(rate_vector(q, tau, "single"), np.full(q, w))
     with pytest.raises(ValueError):
         rate_vector(q, tau, "bgk")
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/cmflb.h compiles as strict C99 (no C++ in the interface) and a
+    C program links against libcmflb and reaches its error path without a
+    device."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "t.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <string.h>\n#include \"cmflb.h\"\n"
+        "int main(void) {\n"
+        "  cmf_desc d;\n  memset(&d, 0, sizeof d);\n"
+        "  int rc = cmf_step(NULL, 1);\n"
+        "  printf(\"%s|%d|%s\\n\", cmf_version(), rc, cmf_last_error());\n"
+        "  return rc == CMF_EINVAL ? 0 : 1;\n}\n")
+    lib = os.path.dirname(_lib.library_path())
+    exe = tmp_path / "t"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(root, "include"), str(src), "-L", lib, "-lcmflb",
+                    f"-Wl,-rpath,{lib}", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    version, rc, err = out.strip().split("|")
+    assert version.startswith("cmflb") and int(rc) == _lib.CMF_EINVAL and "NULL" in err
