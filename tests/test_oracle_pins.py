@@ -277,7 +277,7 @@ def test_reconstruction_paths_agree(q):
         assert np.allclose(T @ a["fstar"], a["kstar"], atol=1e-14)
 
 
-@pytest.mark.parametrize("q", [9, 27])
+@pytest.mark.parametrize("q", [9, 19, 27])
 def test_collision_conserves_mass_and_momentum(q):
     c, _ = O.lattice(q)
     rng = np.random.default_rng(17)
@@ -289,7 +289,7 @@ def test_collision_conserves_mass_and_momentum(q):
         assert np.allclose(c.T @ r["fstar"], c.T @ f, atol=1e-14)
 
 
-@pytest.mark.parametrize("q", [9, 27])
+@pytest.mark.parametrize("q", [9, 19, 27])
 def test_single_site_ou_stationary_variance(q):
     """Iterated noisy collisions at one site: each non-conserved central moment
     is a discrete OU process whose stationary variance is
