@@ -448,3 +448,24 @@ def test_external_buffers_from_torch():
     host = np.zeros(nbytes, dtype=np.uint8)
     with pytest.raises(_lib.CmfError):
         Lattice(q, shape, storage="f32", external=(host.ctypes.data, nbytes))
+
+
+@pytest.mark.parametrize("q,shape", [(9, (1, 1)), (9, (1, 5)), (9, (7, 1)), (9, (2, 2)),
+                                     (27, (1, 1, 1)), (27, (2, 1, 3)), (27, (1, 4, 1)),
+                                     (19, (1, 1, 1)), (19, (3, 1, 2))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_degenerate_boxes_match_oracle(q, shape, storage):
+    """Boxes with edges of 1 or 2 sites (every periodic wrap lands on the
+    site itself or its single neighbour), 9 steps against the oracle."""
+    f0 = _random_state(q, shape, 51)
+    kT, tau, seed, steps = 3e-4, 0.7, 13, 9
+    with Lattice(q, shape, storage=storage, tau=tau, kT=kT, seed=seed) as lat:
+        lat.set_populations(f0)
+        lat.step(steps)
+        got = lat.get_populations()
+        st = lat.stats()
+    f = f0.copy()
+    ref_st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / tau), seed, 0, 0, steps)
+    tol = F64_TOL if storage == "f64" else F32_TOL(steps)
+    assert _rel_err(got, f, q) < tol
+    assert np.allclose(st[:, 1], ref_st[:, 1], rtol=1e-12 if storage == "f64" else 1e-7)
