@@ -323,13 +323,23 @@ def test_mass_and_momentum_conserved_fp64():
     (27, (256, 256, 256), "f16", 8192),    # 16-bit variant, persistent grid
     (19, (256, 256, 256), "f32", None),
     (9, (1024, 1024), "f32", None),
+    (27, (1024, 1024, 1024), "f32", None),  # largest cube whose two buffers fit (232 GB)
 ])
 def test_full_size_sampled_one_step(q, shape, storage, grid):
-    """Full-size lattices in the launch shapes the benchmark times: after 20
-    steps from rest, one more step is checked at sampled sites (random plus
-    every box corner/edge midpoint) against the oracle's single-site
-    collision of the gathered pre-collision populations.  16-bit storage adds
-    one rounding of each deviation to the storage format."""
+    """Full-size lattices in the launch shapes the benchmark times, and the
+    largest D3Q27 cube that fits (2^30 sites, 116 GB per buffer, element
+    offsets beyond 2^32): after 20 steps from rest, one more step is checked
+    at sampled sites (random plus every box corner/edge midpoint) against the
+    oracle's single-site collision of the gathered pre-collision populations.
+    16-bit storage adds one rounding of each deviation to the storage
+    format."""
+    n_all = int(np.prod(shape))
+    need = 2 * q * n_all * {"f32": 4, "f16": 2}[storage]
+    if need > 64 << 30:
+        import torch
+        free, _ = torch.cuda.mem_get_info()
+        if free < need + (4 << 30):
+            pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
     kT, tau, seed = 1e-4, 0.8, 1
     nx, ny = shape[0], shape[1]
     nz = shape[2] if len(shape) == 3 else 1
