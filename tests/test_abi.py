@@ -155,3 +155,28 @@ def test_header_is_plain_c(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     version, rc, err = out.strip().split("|")
     assert version.startswith("cmflb") and int(rc) == _lib.CMF_EINVAL and "NULL" in err
+
+
+def test_ensemble_create_rejects_before_any_device_call():
+    """Host-side checks of cmf_ensemble_create: mixed storage, mixed flags,
+    a replica of 4 GiB or more (tiles address a replica with 32-bit byte
+    offsets) and an invalid member descriptor all fail with CMF_EINVAL."""
+    lib = _lib.load()
+    cases = [
+        ([(9, (16, 16), "f32", 0), (9, (16, 16), "f16", 0)], "storage differs"),
+        ([(9, (16, 16), "f32", 0), (9, (16, 16), "f32", _lib.FLAG_NO_GRAPH)], "flags differ"),
+        ([(27, (1024, 256, 160), "f32", 0)], "below 4 GiB"),
+        ([(9, (16, 16), "f32", 0), (10, (16, 16), "f32", 0)], "q must be"),
+    ]
+    for members, msg in cases:
+        descs = (_lib.Desc * len(members))()
+        keep = []
+        for k, (q, shape, storage, flags) in enumerate(members):
+            d, kp = _lib.make_desc(q, shape, storage=storage, kT=1e-4, flags=flags, replica=k)
+            descs[k] = d
+            keep.append(kp)
+        h = ctypes.c_void_p()
+        rc = lib.cmf_ensemble_create(descs, len(members), None, ctypes.byref(h))
+        assert rc == _lib.CMF_EINVAL, msg
+        assert msg in lib.cmf_last_error().decode()
+        assert not h.value
