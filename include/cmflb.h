@@ -148,7 +148,9 @@ int cmf_destroy(cmf_lattice *lat);
 /* Set the state to the equilibrium f_eq(rho, u) of eq. feq (maximal Hermite
  * order; Sec. 2.2, 2.3) and reset the step counter and statistics.
  * rho: N host doubles or NULL (rho0 everywhere); u: 3 x N host doubles
- * (u_x of all sites, then u_y, then u_z) or NULL (rest).  Synchronous. */
+ * (u_x of all sites, then u_y, then u_z) or NULL (rest).  Synchronous.
+ * Errors: CMF_EINVAL (nothing changed) when a density is not positive and
+ * finite or a velocity component is not finite. */
 int cmf_init_equilibrium(cmf_lattice *lat, const double *rho, const double *u);
 
 /* Overwrite the pre-collision populations f_i(x, t) of the current step with
@@ -221,7 +223,7 @@ int cmf_get_step(cmf_lattice *lat, int64_t *step);
  * init), oldest first, at most min(cap, series_capacity) of them (the most
  * recent ones); *n_out receives the count.  Synchronises.  Returns
  * CMF_ENONFINITE (after filling `out`) when one of the returned rows counts
- * non-finite sites. */
+ * non-finite sites, CMF_EINVAL when cap < 0. */
 int cmf_stats(cmf_lattice *lat, cmf_moments *out, int64_t cap,
               int64_t *n_out);
 
@@ -353,8 +355,8 @@ int cmf_ensemble_autotune(cmf_ensemble *ens, int32_t steps_per_trial,
                           cmf_ensemble_tiles *trials, int32_t cap, int32_t *n_out);
 
 /* Replica `index` (creation order) to f_eq(rho, u), with the arguments of
- * cmf_init_equilibrium.  The shared step counter is not changed.
- * Synchronous. */
+ * cmf_init_equilibrium (and its CMF_EINVAL checks).  The shared step
+ * counter is not changed.  Synchronous. */
 int cmf_ensemble_init_equilibrium(cmf_ensemble *ens, int32_t index,
                                   const double *rho, const double *u);
 

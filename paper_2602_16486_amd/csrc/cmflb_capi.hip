@@ -567,6 +567,55 @@ int cmf_device_count(void) {
 
 namespace {
 
+// host checks of the fields of an equilibrium initialisation: positive
+// finite densities, finite velocities
+int check_init_fields(int64_t N, const double *rho, const double *u) {
+  if (rho)
+    for (int64_t s = 0; s < N; ++s)
+      if (!(rho[s] > 0.0) || !isfinite(rho[s]))
+        return fail(CMF_EINVAL, "rho[%lld] = %g is not a positive density", (long long)s, rho[s]);
+  if (u)
+    for (int64_t s = 0; s < 3 * N; ++s)
+      if (!isfinite(u[s]))
+        return fail(CMF_EINVAL, "u[%lld] = %g is not finite", (long long)s, u[s]);
+  return CMF_OK;
+}
+
+// device copies of the optional rho (N) and u (3 N) fields; on failure
+// nothing stays allocated
+hipError_t upload_init_fields(int64_t N, const double *rho, const double *u, double **drho,
+                              double **du) {
+  *drho = *du = nullptr;
+  hipError_t e = hipSuccess;
+  if (rho) {
+    e = hipMalloc((void **)drho, sizeof(double) * N);
+    if (e == hipSuccess) e = hipMemcpy(*drho, rho, sizeof(double) * N, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && u) {
+    e = hipMalloc((void **)du, sizeof(double) * 3 * N);
+    if (e == hipSuccess) e = hipMemcpy(*du, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    if (*drho) (void)hipFree(*drho);
+    if (*du) (void)hipFree(*du);
+    *drho = *du = nullptr;
+  }
+  return e;
+}
+
+// timing events, all or none
+int create_events(std::vector<hipEvent_t> &ev) {
+  for (auto &x : ev) {
+    const hipError_t e = hipEventCreate(&x);
+    if (e != hipSuccess) {
+      for (auto &y : ev)
+        if (y) (void)hipEventDestroy(y);
+      return fail(CMF_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+  }
+  return CMF_OK;
+}
+
 // bytes of one population buffer (q x N elements, rounded up to 256)
 size_t buffer_bytes(const cmf_desc *d) {
   return ((size_t)d->q * d->nx * d->ny * d->nz * storage_bytes(d->storage) + 255) / 256 * 256;
@@ -719,25 +768,15 @@ int cmf_destroy(cmf_lattice *L) {
 
 int cmf_init_equilibrium(cmf_lattice *L, const double *rho, const double *u) {
   if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  int rc = check_init_fields(L->N, rho, u);
+  if (rc != CMF_OK) return rc;
   HIP_TRY(hipStreamSynchronize(L->stream));
   double *drho = nullptr, *du = nullptr;
-  const int64_t N = L->N;
-  if (rho) {
-    for (int64_t s = 0; s < N; ++s)
-      if (!(rho[s] > 0.0) || !isfinite(rho[s]))
-        return fail(CMF_EINVAL, "rho[%lld] = %g is not a positive density", (long long)s, rho[s]);
-    HIP_TRY(hipMalloc((void **)&drho, sizeof(double) * N));
-    HIP_TRY(hipMemcpy(drho, rho, sizeof(double) * N, hipMemcpyHostToDevice));
+  hipError_t e = upload_init_fields(L->N, rho, u, &drho, &du);
+  if (e == hipSuccess) {
+    L->parity = 0;
+    e = launch_init_eq(L->q, L->storage, L->cp, drho, du, L->buf[0], L->stream);
   }
-  if (u) {
-    if (hipMalloc((void **)&du, sizeof(double) * 3 * N) != hipSuccess) {
-      if (drho) (void)hipFree(drho);
-      return fail(CMF_ENOMEM, "hipMalloc of the velocity field failed");
-    }
-    HIP_TRY(hipMemcpy(du, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
-  }
-  L->parity = 0;
-  hipError_t e = launch_init_eq(L->q, L->storage, L->cp, drho, du, L->buf[0], L->stream);
   if (e == hipSuccess) e = launch_zero_i64(L->step_dev, 1, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (drho) (void)hipFree(drho);
@@ -828,8 +867,8 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
   *kernel_ms = 0.0;
   if (nsteps == 0) return CMF_OK;
   std::vector<hipEvent_t> ev(2 * nsteps, nullptr);
-  for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-  int rc = CMF_OK;
+  int rc = create_events(ev);
+  if (rc != CMF_OK) return rc;
   for (int64_t s = 0; s < nsteps && rc == CMF_OK; ++s) {
     const void *src = L->buf[L->parity];
     void *dst = L->buf[1 - L->parity];
@@ -1071,6 +1110,7 @@ int cmf_get_step(cmf_lattice *L, int64_t *step) {
 
 int cmf_stats(cmf_lattice *L, cmf_moments *out, int64_t cap, int64_t *n_out) {
   if (!L || !n_out || (cap > 0 && !out)) return fail(CMF_EINVAL, "NULL argument");
+  if (cap < 0) return fail(CMF_EINVAL, "cap < 0");
   *n_out = 0;
   int64_t step = 0;
   int rc = cmf_get_step(L, &step);
@@ -1680,22 +1720,11 @@ int cmf_ensemble_init_equilibrium(cmf_ensemble *E, int32_t index, const double *
   int rc = ens_check_index(E, index);
   if (rc != CMF_OK) return rc;
   cmf_ensemble::Rep &rp = E->reps[index];
+  rc = check_init_fields(rp.N, rho, u);
+  if (rc != CMF_OK) return rc;
   HIP_TRY(hipStreamSynchronize(E->stream));
-  const int64_t N = rp.N;
   double *drho = nullptr, *du = nullptr;
-  if (rho)
-    for (int64_t s = 0; s < N; ++s)
-      if (!(rho[s] > 0.0) || !isfinite(rho[s]))
-        return fail(CMF_EINVAL, "rho[%lld] = %g is not a positive density", (long long)s, rho[s]);
-  hipError_t e = hipSuccess;
-  if (rho) {
-    e = hipMalloc((void **)&drho, sizeof(double) * N);
-    if (e == hipSuccess) e = hipMemcpy(drho, rho, sizeof(double) * N, hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess && u) {
-    e = hipMalloc((void **)&du, sizeof(double) * 3 * N);
-    if (e == hipSuccess) e = hipMemcpy(du, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
-  }
+  hipError_t e = upload_init_fields(rp.N, rho, u, &drho, &du);
   if (e == hipSuccess)
     e = launch_init_eq(rp.desc.q, E->storage, rp.cp, drho, du, ens_replica_buffer(E, index), E->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
@@ -1764,7 +1793,8 @@ int cmf_ensemble_profile_steps(cmf_ensemble *E, int64_t nsteps, double *kernel_m
   if (nsteps < 0) return fail(CMF_EINVAL, "nsteps < 0");
   *kernel_ms = 0.0;
   std::vector<hipEvent_t> ev(2 * nsteps, nullptr);
-  for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
+  const int rc = create_events(ev);
+  if (rc != CMF_OK) return rc;
   hipError_t e = hipSuccess;
   for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
     e = hipEventRecord(ev[2 * s], E->stream);
@@ -1809,6 +1839,7 @@ int cmf_ensemble_stats(cmf_ensemble *E, int32_t index, cmf_moments *out, int64_t
   int rc = ens_check_index(E, index);
   if (rc != CMF_OK) return rc;
   if (!n_out || (cap > 0 && !out)) return fail(CMF_EINVAL, "NULL argument");
+  if (cap < 0) return fail(CMF_EINVAL, "cap < 0");
   *n_out = 0;
   int64_t step = 0;
   rc = cmf_ensemble_get_step(E, &step);

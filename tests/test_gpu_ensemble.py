@@ -238,3 +238,26 @@ def test_aligned_replicas_match_standalone_lattices(storage):
             lat.set_populations(states[k])
             lat.step(35)
             assert np.array_equal(got[k], lat.get_populations()), f"replica {k}"
+
+
+def test_invalid_fields_and_cap_leave_the_ensemble_unchanged():
+    """cmf_ensemble_init_equilibrium applies cmf_init_equilibrium's checks and
+    cmf_ensemble_stats rejects a negative cap; neither changes any replica."""
+    import ctypes
+    with Ensemble(REPLICAS[:2], storage="f32") as ens:
+        ens.step(2)
+        before = [ens.get_populations(k) for k in range(2)]
+        n = ens.sizes[1]
+        u = np.zeros((3, n))
+        u[2, n - 1] = np.inf
+        with pytest.raises(_lib.CmfError) as exc:
+            ens.init_equilibrium(1, u=u)
+        assert exc.value.code == _lib.CMF_EINVAL and "not finite" in str(exc.value)
+        with pytest.raises(_lib.CmfError) as exc:
+            ens.init_equilibrium(0, rho=np.zeros(ens.sizes[0]))
+        assert exc.value.code == _lib.CMF_EINVAL
+        cnt = ctypes.c_int64(7)
+        assert ens._lib.cmf_ensemble_stats(ens._h, 0, None, -1, ctypes.byref(cnt)) == _lib.CMF_EINVAL
+        for k in range(2):
+            assert np.array_equal(ens.get_populations(k), before[k])
+            assert np.array_equal(ens.stats(k)[:, 0], np.arange(2))

@@ -305,6 +305,32 @@ def test_nonfinite_is_reported():
         assert exc.value.code == _lib.CMF_ENONFINITE
 
 
+def test_invalid_fields_and_cap_leave_the_lattice_unchanged():
+    """cmf_init_equilibrium rejects a non-positive density and a non-finite
+    velocity, and cmf_stats a negative cap, with CMF_EINVAL before touching
+    the state: populations, step counter and unread statistics survive."""
+    import ctypes
+    shape = (16, 12)
+    n = W.n_sites(shape)
+    with Lattice(9, shape, storage="f32", kT=1e-4, seed=4) as lat:
+        lat.step(3)
+        f = lat.get_populations()
+        rho = np.ones(n)
+        rho[5] = -1.0
+        u = np.zeros((3, n))
+        u[1, 7] = np.nan
+        for kw, msg in (({"rho": rho}, "positive density"), ({"u": u}, "not finite")):
+            with pytest.raises(_lib.CmfError) as exc:
+                lat.init_equilibrium(**kw)
+            assert exc.value.code == _lib.CMF_EINVAL and msg in str(exc.value)
+        cnt = ctypes.c_int64(7)
+        assert lat._lib.cmf_stats(lat._h, None, -1, ctypes.byref(cnt)) == _lib.CMF_EINVAL
+        assert b"cap < 0" in lat._lib.cmf_last_error()
+        assert lat.step_index == 3
+        assert np.array_equal(lat.get_populations(), f)
+        assert np.array_equal(lat.stats()[:, 0], np.arange(3))
+
+
 def test_mass_and_momentum_conserved_fp64():
     q, shape = 27, (24, 20, 16)
     f0 = _random_state(q, shape, 47)
