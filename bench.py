@@ -108,7 +108,7 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
 
 
 def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
-    """Config 5: 256 D2Q9 replicas (edges uniform in [32, 512] per axis) and
+    """The mixed ensemble: 256 D2Q9 replicas (edges uniform in [32, 512] per axis) and
     64 D3Q27 replicas (edges uniform in [32, 96]), each with its own seed,
     kT log-uniform in [1e-6, 1e-3] and tau uniform in [0.502, 2.0], FP32,
     one launch per step; compared with the same replicas stepped one

@@ -35,6 +35,9 @@ class Ensemble:
                                                  ctypes.byref(handle)))
         self._h = handle
         self.n = len(replicas)
+        # steps each replica's statistics ring holds (the library's default
+        # when 0); no call can return more rows
+        self._ring = int(series_capacity) if int(series_capacity) > 0 else 4096
 
     def close(self):
         if getattr(self, "_h", None):
@@ -117,6 +120,9 @@ class Ensemble:
         return v.value
 
     def stats(self, index, cap=1 << 16, raise_nonfinite=True):
+        """Statistics rows of replica ``index`` since the previous call, as
+        :meth:`Lattice.stats`."""
+        cap = max(0, min(int(cap), self._ring))
         buf = (_lib.Moments * cap)()
         n = ctypes.c_int64()
         rc = self._lib.cmf_ensemble_stats(self._h, index, buf, cap, ctypes.byref(n))

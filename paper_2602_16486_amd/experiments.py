@@ -1,11 +1,13 @@
 """Statistical validation runs on the GPU: the paper's Tests 3-7 (Sec. 3)
-and the larger configurations of the project's benchmark plan, all on
-synthetic rest-state inputs.  Each run prints one JSON line.
+and larger runs of the same method (a D2Q9 1024^2 kT x tau sweep, D3Q27
+128^3 at three densities, D3Q27 256^3 with 16-bit storage, the mixed
+320-replica ensemble), all on synthetic rest-state inputs.  Each run
+prints one JSON line.
 
     python -m paper_2602_16486_amd.experiments NAME [--scale S]
 
-NAME: test2 tg3d test3 test4 test5 test6 test7 d3q19 config2 config3 config4
-config5, or all.
+NAME: test2 tg3d test3 test4 test5 test6 test7 d3q19 d2q9_1024_sweep
+d3q27_128_rho0 d3q27_256_storage ensemble_mixed_320, or all.
 --scale multiplies the number of steps (default 1; the paper's durations
 are used at scale 1 where they are stated).
 """
@@ -215,7 +217,7 @@ def d3q19(scale):
         _emit({"experiment": "d3q19", "box": name, "shape": shape, "steps": steps, **r})
 
 
-def config2(scale):
+def d2q9_1024_sweep(scale):
     """D2Q9 1024^2, FP32 and FP64 storage, kT x tau grid, 20000 steps,
     averages and S(k) (every 100 steps) over steps 10000-20000."""
     for storage in ("f32", "f64"):
@@ -228,18 +230,18 @@ def config2(scale):
                 # spectrum beyond the first three shells separately
                 shells = np.array(r["S_u_shells"])
                 r["S_u_max_dev_beyond_3_shells"] = float(np.abs(shells[3:] - 1).max())
-                _emit({"experiment": "config2", "storage": storage, "kT": kT, "tau": tau, **r})
+                _emit({"experiment": "d2q9_1024_sweep", "storage": storage, "kT": kT, "tau": tau, **r})
 
 
-def config3(scale):
+def d3q27_128_rho0(scale):
     """D3Q27 128^3, rho0 in {0.5, 1, 2}, tau = 0.55, kT = 1e-4, 10000 steps,
     averages over steps 2000-10000: isotropy and 1/rho0 scaling."""
     for rho0 in (0.5, 1.0, 2.0):
         r = run(27, (128, 128, 128), steps=int(10_000 * scale), tau=0.55, kT=1e-4, rho0=rho0, window=0.8)
-        _emit({"experiment": "config3", "rho0": rho0, **r})
+        _emit({"experiment": "d3q27_128_rho0", "rho0": rho0, **r})
 
 
-def config4(scale):
+def d3q27_256_storage(scale):
     """D3Q27 256^3, FP32 / FP16 / BF16 storage (same noise), tau in
     {0.51, 0.8}, kT in {1e-5, 1e-4}: <u^2> and S(k) of the 16-bit runs
     against the FP32 run."""
@@ -250,7 +252,7 @@ def config4(scale):
             for storage in ("f32", "f16", "bf16"):
                 r = run(27, (256, 256, 256), storage=storage, steps=steps, tau=tau, kT=kT,
                         sk_every=50, nbins=48)
-                rec = {"experiment": "config4", "storage": storage, "tau": tau, "kT": kT, "steps": steps}
+                rec = {"experiment": "d3q27_256_storage", "storage": storage, "tau": tau, "kT": kT, "steps": steps}
                 shells = np.array(r.pop("S_u_shells"))
                 u2 = float(np.mean(r["u2_over_target"]))
                 if ref_u2 is None:
@@ -261,7 +263,7 @@ def config4(scale):
                 _emit({**rec, **r})
 
 
-def config5(scale):
+def ensemble_mixed_320(scale):
     """The batched ensemble (256 D2Q9 + 64 D3Q27 replicas), 5000 steps:
     per-replica equipartition over steps 2500-5000."""
     manifest = W.ensemble_manifest()
@@ -294,14 +296,15 @@ def config5(scale):
             else:
                 outliers.append({"index": k, "q": r["q"], "shape": list(r["shape"]), "kT": r["kT"],
                                  "tau": r["tau"], "ratio": ratio, "band": band})
-    _emit({"experiment": "config5", "replicas": len(manifest), "steps": steps, "seconds": secs,
+    _emit({"experiment": "ensemble_mixed_320", "replicas": len(manifest), "steps": steps, "seconds": secs,
            "u2_over_target_median": float(np.median(ratios)),
            "u2_over_target_min_max": [float(min(ratios)), float(max(ratios))],
            "replicas_within_band": int(inband), "outside_band": outliers})
 
 
-EXPERIMENTS = {f.__name__: f for f in (test2, tg3d, test3, test4, test5, test6, test7, d3q19, config2, config3,
-                                        config4, config5)}
+EXPERIMENTS = {f.__name__: f for f in (test2, tg3d, test3, test4, test5, test6, test7, d3q19,
+                                        d2q9_1024_sweep, d3q27_128_rho0, d3q27_256_storage,
+                                        ensemble_mixed_320)}
 
 
 def main(argv=None):

@@ -51,7 +51,7 @@ def external_bytes(q, shape, storage="f32"):
 
 
 class Lattice:
-    """A periodic D2Q9 or D3Q27 box stepped by the fused CM-FLBM kernel.
+    """A periodic D2Q9, D3Q19 or D3Q27 box stepped by the fused CM-FLBM kernel.
 
     ``shape`` is (nx, ny) or (nx, ny, nz); ``storage`` one of f64, f32, f16,
     bf16; ``lam`` optional per-mode relaxation rates (default: the paper's);
@@ -83,6 +83,9 @@ class Lattice:
         d.seed = int(seed)
         d.replica = int(replica)
         d.series_capacity = int(series_capacity)
+        # the statistics ring holds this many steps (the library's default
+        # when 0); no call can return more rows
+        self._ring = int(series_capacity) if int(series_capacity) > 0 else 4096
         self.rho0, self.tau, self.kT = float(rho0), float(tau), float(kT)
         handle = ctypes.c_void_p()
         if external is None:
@@ -216,7 +219,9 @@ class Lattice:
 
     def stats(self, cap=1 << 20, raise_nonfinite=True):
         """(n, 12) array of the per-step statistics rows recorded since the
-        previous call (columns ``_lib.STAT_COLUMNS``)."""
+        previous call (columns ``_lib.STAT_COLUMNS``), at most the last
+        min(cap, series capacity) of them."""
+        cap = max(0, min(int(cap), self._ring))
         buf = (_lib.Moments * cap)()
         n = ctypes.c_int64()
         rc = self._lib.cmf_stats(self._h, buf, cap, ctypes.byref(n))

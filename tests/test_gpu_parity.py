@@ -171,7 +171,7 @@ def test_one_step_16bit_matches_oracle(q, shape, storage, general):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_config1_prefix_matches_oracle(storage):
+def test_d2q9_64_prefix_matches_oracle(storage):
     """D2Q9 64x64, rho0 = 1, tau = 0.8, kT = 1e-4, Philox seed 1, from rest:
     the first 200 steps against the oracle, fields and statistics."""
     q, shape, kT, steps = 9, (64, 64), 1e-4, 200
@@ -183,7 +183,7 @@ def test_config1_prefix_matches_oracle(storage):
     ref = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), 1, 0, 0, steps)
     tol = F64_TOL if storage == "f64" else F32_TOL(steps)
     err = _rel_err(got, f, q)
-    print(f"config1 prefix {storage}: rel err {err:.3e} (tol {tol:.1e})")
+    print(f"D2Q9 64^2 prefix {storage}: rel err {err:.3e} (tol {tol:.1e})")
     assert err < tol
     assert np.array_equal(st[:, 0], np.arange(steps))
     rtol = 1e-10 if storage == "f64" else 50 * F32_TOL(steps)

@@ -1,5 +1,5 @@
-"""The benchmark configurations at sizes the oracle finishes in seconds:
-config 1 in full (D2Q9 64^2, 2000 steps) and a 48^3 subrun of config 4
+"""Whole runs at sizes the oracle finishes in seconds: D2Q9 64^2 in full
+(2000 steps) and a D3Q27 48^3 run standing in for the 256^3 benchmark box
 (FP32 / FP16 / BF16 storage against the FP64 oracle).  Needs an MI355X."""
 import math
 
@@ -20,7 +20,7 @@ def _gpu_present():
 
 
 @pytest.fixture(scope="module")
-def config1_oracle():
+def d2q9_64_oracle():
     q, shape, kT, steps = 9, (64, 64), 1e-4, 2000
     f = O.init_equilibrium(q, 4096, rho0=1.0)
     st = O.run(q, shape, f, kT, O.paper_lambda(q, 1 / 0.8), 1, 0, 0, steps)
@@ -28,11 +28,11 @@ def config1_oracle():
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_config1_full_run(storage, config1_oracle):
+def test_d2q9_64_full_run(storage, d2q9_64_oracle):
     """D2Q9 64x64, rho0 = 1, tau = 0.8, kT = 1e-4, Philox seed 1, 2000 steps
     from rest: fields against the oracle, equipartition, conservation."""
     q, shape, kT, steps = 9, (64, 64), 1e-4, 2000
-    f_ref, st_ref = config1_oracle
+    f_ref, st_ref = d2q9_64_oracle
     with Lattice(q, shape, storage=storage, tau=0.8, kT=kT, seed=1) as lat:
         lat.step(steps)
         got = lat.get_populations()
@@ -40,7 +40,7 @@ def test_config1_full_run(storage, config1_oracle):
     _, w = O.lattice(q)
     err = np.abs(got - f_ref).max() / np.abs(f_ref - w[:, None]).max()
     tol = 1e-11 if storage == "f64" else 3e-6 * (1 + math.sqrt(steps))
-    print(f"config1 {storage}: rel err after {steps} steps {err:.3e} (tol {tol:.1e})")
+    print(f"D2Q9 64^2 {storage}: rel err after {steps} steps {err:.3e} (tol {tol:.1e})")
     assert err < tol
     eq = S.equipartition(st, 4096, kT, 1.0, 2, start=200)
     eq_ref = S.equipartition(st_ref, 4096, kT, 1.0, 2, start=200)
@@ -53,7 +53,7 @@ def test_config1_full_run(storage, config1_oracle):
 
 
 @pytest.fixture(scope="module")
-def config4_subrun_oracle():
+def d3q27_48_oracle():
     q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
     n = 48 ** 3
     f = O.init_equilibrium(q, n, 1.0)
@@ -67,12 +67,12 @@ def config4_subrun_oracle():
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_config4_subrun_against_oracle(storage, config4_subrun_oracle):
+def test_d3q27_48_storage_against_oracle(storage, d3q27_48_oracle):
     """48^3 subrun of the 256^3 storage comparison: <u^2> (averaged over the
     run) within 1% of the FP64 oracle for every storage type, and the
     structure factor shells within 2% (FP32 within 1e-4)."""
     q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
-    st_ref, sk_ref = config4_subrun_oracle
+    st_ref, sk_ref = d3q27_48_oracle
     with Lattice(q, shape, storage=storage, tau=tau, kT=kT, seed=1) as lat:
         lat.sk_reset(16)
         for _ in range(steps // every):
@@ -86,9 +86,9 @@ def test_config4_subrun_against_oracle(storage, config4_subrun_oracle):
     rel = abs(u2[20:].mean() / u2_ref[20:].mean() - 1)
     # step 0 is the rest state (u = 0 on both sides)
     per_step = np.abs(u2[1:] / u2_ref[1:] - 1).max()
-    print(f"config4 subrun {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
+    print(f"D3Q27 48^3 {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
     assert rel < (1e-4 if storage == "f32" else 1e-2)
     sel = sk_ref[:, 1] > 0
     srel = np.abs(sk[sel, 2:5] / sk_ref[sel, 2:5] - 1).max()
-    print(f"config4 subrun {storage}: S(k) worst shell rel diff {srel:.2e}")
+    print(f"D3Q27 48^3 {storage}: S(k) worst shell rel diff {srel:.2e}")
     assert srel < (1e-4 if storage == "f32" else 2e-2)

@@ -64,7 +64,7 @@ def test_zero_noise_rest_state_is_exact(q, shape):
     assert np.abs(st[:, 8:11]).max() / n < 1e-31
 
 
-def test_equipartition_config1():
+def test_equipartition_d2q9_64():
     """Test 3 on a 64x64 D2Q9 box (rho0 = 1, tau = 0.8, kT = 1e-4, seed 1, 2000
     steps): <u_a^2> = kT/rho0 (1 - 1/N) for both components; the per-step
     RMS deviation is the white-noise value sqrt(2/N) kT/rho0, which is also
