@@ -246,7 +246,73 @@ def variants_summary(outdir):
     print("\n".join(lines))
 
 
+VALU_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_SALU "
+                 "SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE")
+CMD_VALU = ("CMFLB_TUNE_CACHE=out/tune.txt rocprofv3 --pmc " + VALU_COUNTERS + " -d out/prof_valu -o valu --output-format csv "
+            "-- python3 bench.py --steps 10 --warmup 8 --no-cpu --no-tune --no-ensemble")
+CU_NUM = 256
+XCC_NUM = 8
+
+
+def valu_summary(outdir):
+    """profiles/k_step_valu_256cube.md: vector-ALU activity of every step
+    kernel at 256^3 from one counter pass.  VALU busy is rocprofv3's VALUBusy,
+    100 sum(SQ_ACTIVE_INST_VALU) / CU_NUM / max(GRBM_GUI_ACTIVE), where
+    SQ_ACTIVE_INST_VALU counts quad-cycles (one wave64 instruction on a
+    16-lane SIMD) summed over all SIMDs, and the per-dispatch
+    GRBM_GUI_ACTIVE reading is the sum over the 8 XCDs (max = sum / 8)."""
+    path = os.path.join(outdir, "prof_valu", "valu_counter_collection.csv")
+    if not os.path.exists(path):
+        return
+    vals = {}
+    launch = {}
+    for r in csv.DictReader(open(path)):
+        for prefix, label, q, sbytes, _ in VARIANTS:
+            if r["Kernel_Name"].startswith(prefix):
+                vals.setdefault(label, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                launch[label] = (int(r["Workgroup_Size"]), int(r["Grid_Size"]) // int(r["Workgroup_Size"]))
+    lines = [
+        "# k_step vector-ALU activity at 256^3 — rocprofv3 counter summary",
+        "",
+        "Workload: as in `k_step_variants_256cube.md` (256^3, rest start, rho0=1, tau=0.8, kT=1e-4, "
+        "Philox seed 1); launch shapes from the tuning cache of a preceding `python bench.py --no-cpu "
+        "--no-ensemble` run (`CMFLB_TUNE_CACHE` set for both).",
+        "",
+        "Command (repository root on a machine with an MI355X, after `cd /tmp && export TMPDIR=/tmp`):",
+        "",
+        "    CMFLB_TUNE_CACHE=out/tune.txt python3 bench.py --no-cpu --no-ensemble > out/tune_run.json",
+        "    " + CMD_VALU,
+        "    python profile_summary.py out",
+        "",
+        "Medians over all dispatches of each kernel.  VALU instructions per site = SQ_INSTS_VALU x 64 / 256^3 "
+        "(each wave instruction serves 64 sites); quad-cycles per instruction = SQ_ACTIVE_INST_VALU / "
+        "SQ_INSTS_VALU (1 = a full-rate wave64 instruction); VALU busy = rocprofv3's VALUBusy, "
+        "100 sum(SQ_ACTIVE_INST_VALU) / 256 CUs / max(GRBM_GUI_ACTIVE), with the per-dispatch GRBM_GUI_ACTIVE "
+        "summed over the 8 XCDs (max = sum / 8).",
+        "",
+        "| kernel | launch (block, grid) | VALU instr / site | SALU instr / wave (64 sites) | quad-cycles / VALU instr | "
+        "GPU cycles (per XCD) | VALU busy |",
+        "|---|---|---|---|---|---|---|",
+    ]
+    for prefix, label, q, sbytes, _ in VARIANTS:
+        c = vals.get(label)
+        if not c:
+            continue
+        med = {k: statistics.median(v) for k, v in c.items()}
+        per_xcd = med["GRBM_GUI_ACTIVE"] / XCC_NUM
+        busy = 100 * med["SQ_ACTIVE_INST_VALU"] / CU_NUM / per_xcd
+        lines.append(f"| {label} | {launch[label]} | {med['SQ_INSTS_VALU'] * 64 / N:.0f} | "
+                     f"{med['SQ_INSTS_SALU'] * 64 / N:.0f} | "
+                     f"{med['SQ_ACTIVE_INST_VALU'] / med['SQ_INSTS_VALU']:.3f} | {per_xcd:.4g} | {busy:.0f} % |")
+    lines += ["", "About 100 % VALU busy means the vector ALUs issue every cycle: the 16-bit kernels are bound by "
+              "instruction issue (noise generation and the FP32 collision), the FP32 kernels by HBM.", ""]
+    with open(os.path.join(ROOT, "profiles", "k_step_valu_256cube.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     main(sys.argv[1] if len(sys.argv) > 1 else "out")
     ensemble_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
     variants_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
+    valu_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
