@@ -32,7 +32,7 @@ def _gpu_present():
     assert _lib.device_count() > 0, "no HIP device visible: the gpu tests need an MI355X"
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
 def test_replicas_match_standalone_lattices(storage):
     steps = 40  # one captured 32-step graph + 8 direct steps
     states = [_state(r, 100 + k) for k, r in enumerate(REPLICAS)]
@@ -222,7 +222,7 @@ ALIGNED = [  # every population row a whole number of 128-byte lines in FP32 and
 ]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_aligned_replicas_match_standalone_lattices(storage):
     """Ensembles whose rows are all whole cache lines take the non-temporal
     store and c_x = 0 load path; replicas still equal standalone lattices."""
