@@ -291,7 +291,6 @@ def gen_populations(L, r, d):
         return (w / b[v]) * r[v]
 
     out = [None] * 19
-    out[0] = S.define("p0", a(0, w0) - a(4, w0) + a(16, w0))
     # axis orbits, |c|^2 = 1: even parts C + 2P, C - P + Q, C - P - Q
     C = S.define("pc", a(0, w1) - 2 * a(16, w1))
     P = S.define("pp", a(5, w1) - a(17, w1))
@@ -328,6 +327,15 @@ def gen_populations(L, r, d):
                 c = [0, 0, 0]
                 c[ax], c[bx] = sa, sb
                 out[L.C.index(tuple(c))] = (e1 + sa * o1) if sa == sb else (e2 + sa * o2)
+    # rest population: r_0 minus the other 18, whose sum is 2 (sum of the
+    # axis even parts) + 4 (sum of the face-diagonal even parts).  Equal to
+    # w_0 sum_v P_v(0) r_v / b_v, but the stored populations then sum to
+    # r_0 up to unbiased rounding: the rounded constants w_0 / b_v, w_1 / b_v,
+    # w_2 / b_v of the direct formula leave a fixed fraction of r_4 and r_16
+    # (whose means are O(rho u^2), i.e. O(kT)) in the mass, a drift linear in
+    # the number of steps in FP32.
+    rest = S.define("prest", 2 * (even[0] + even[1] + even[2]) + 4 * (E2[(0, 1)] + E2[(0, 2)] + E2[(1, 2)]))
+    out[0] = r[0] - rest
     for i in range(19):
         assert sp.expand(S.expand(out[i]) - sum(L.Minv[i, v] * r[v] for v in range(19))) == 0, i
     return S.lines() + [f"  d[{i}] = {_PRINT.doprint(out[i])};" for i in range(19)]

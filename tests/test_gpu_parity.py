@@ -400,6 +400,52 @@ def test_full_size_sampled_one_step(q, shape, storage, grid):
     assert worst <= 1.0
 
 
+@pytest.mark.parametrize("q,shape,storage,grid", [
+    (27, (256, 256, 256), "f32", None),    # the benchmark: one workgroup per tile
+    (27, (256, 256, 256), "f16", 8192),    # 16-bit variant, persistent grid
+    (19, (256, 256, 256), "f32", None),
+    (9, (1024, 1024), "f32", None),
+])
+def test_full_size_rest_state_and_conservation(q, shape, storage, grid):
+    """Whole-box properties at full size, in the benchmark's launch shapes,
+    over 40 steps (one captured 32-step graph and 8 direct steps): from rest
+    with kT = 0 every site stays exactly at rest (the FP64 sums of rho - rho0,
+    rho u, u and u^2 are exactly zero); with kT = 1e-4 total mass and momentum
+    stay within the random walk of the storage rounding, 6 sqrt(N T q) eps
+    sigma with sigma = sqrt(rho0 kT w_0 / c_s^2) and eps = 2^-24 (FP32) or
+    2^-11 (FP16, relative to the scaled value), since the collision conserves
+    both exactly and streaming permutes the populations."""
+    n = W.n_sites(shape)
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) == 3 else 1
+    steps = 40
+    launch = (256, grid if grid else (nx + 255) // 256 * ny * nz)
+    with Lattice(q, shape, storage=storage, tau=0.8, kT=0.0, seed=1) as lat:
+        lat.set_launch(*launch)
+        lat.step(steps)
+        st = lat.stats()
+    assert np.array_equal(st[:, 0], np.arange(steps))
+    assert np.all(st[:, 1] == n * 1.0)
+    assert not np.any(st[:, 2:])
+    kT = 1e-4
+    _, w = O.lattice(q)
+    sigma = math.sqrt(kT * w[0] * 3)
+    eps = {"f32": 2 ** -24, "f16": 2 ** -11}[storage]
+    bound = 6 * math.sqrt(n * steps * q) * eps * sigma
+    with Lattice(q, shape, storage=storage, tau=0.8, kT=kT, seed=1) as lat:
+        lat.set_launch(*launch)
+        lat.step(steps)
+        st = lat.stats()
+    assert np.array_equal(st[:, 0], np.arange(steps))
+    assert not np.any(st[:, 11])
+    drift = np.abs(st[:, 1] - n).max()
+    mom = np.abs(st[:, 2:5]).max()
+    print(f"{shape} q={q} {storage}: mass drift {drift:.2e}, momentum {mom:.2e}, bound {bound:.2e}")
+    assert drift < bound and mom < bound
+    # and the noise is on: <u^2> has grown to a sizeable part of kT / rho0
+    assert st[-1, 8:11].sum() / (3 * n) > 0.1 * kT
+
+
 @pytest.mark.parametrize("q,shape,storage", [(9, (19, 7), "f64"), (27, (9, 6, 5), "f64"), (27, (9, 6, 5), "f32")])
 def test_get_macro_matches_populations(q, shape, storage):
     """cmf_get_macro: rho = sum f and u = sum c f / rho of the pre-collision
