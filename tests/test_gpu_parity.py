@@ -403,7 +403,9 @@ def test_full_size_sampled_one_step(q, shape, storage, grid):
 @pytest.mark.parametrize("q,shape,storage,grid", [
     (27, (256, 256, 256), "f32", None),    # the benchmark: one workgroup per tile
     (27, (256, 256, 256), "f16", 8192),    # 16-bit variant, persistent grid
+    (27, (256, 256, 256), "bf16", 8192),
     (19, (256, 256, 256), "f32", None),
+    (19, (256, 256, 256), "f16", 4096),
     (9, (1024, 1024), "f32", None),
 ])
 def test_full_size_rest_state_and_conservation(q, shape, storage, grid):
@@ -412,9 +414,10 @@ def test_full_size_rest_state_and_conservation(q, shape, storage, grid):
     with kT = 0 every site stays exactly at rest (the FP64 sums of rho - rho0,
     rho u, u and u^2 are exactly zero); with kT = 1e-4 total mass and momentum
     stay within the random walk of the storage rounding, 6 sqrt(N T q) eps
-    sigma with sigma = sqrt(rho0 kT w_0 / c_s^2) and eps = 2^-24 (FP32) or
-    2^-11 (FP16, relative to the scaled value), since the collision conserves
-    both exactly and streaming permutes the populations."""
+    sigma with sigma = sqrt(rho0 kT w_0 / c_s^2) and eps = 2^-24 (FP32),
+    2^-11 (FP16) or 2^-8 (BF16; relative to the scaled value), since the
+    collision conserves both exactly and streaming permutes the populations.
+    A systematic error (a drift linear in the steps) exceeds it at once."""
     n = W.n_sites(shape)
     nx, ny = shape[0], shape[1]
     nz = shape[2] if len(shape) == 3 else 1
@@ -430,7 +433,7 @@ def test_full_size_rest_state_and_conservation(q, shape, storage, grid):
     kT = 1e-4
     _, w = O.lattice(q)
     sigma = math.sqrt(kT * w[0] * 3)
-    eps = {"f32": 2 ** -24, "f16": 2 ** -11}[storage]
+    eps = {"f32": 2 ** -24, "f16": 2 ** -11, "bf16": 2 ** -8}[storage]
     bound = 6 * math.sqrt(n * steps * q) * eps * sigma
     with Lattice(q, shape, storage=storage, tau=0.8, kT=kT, seed=1) as lat:
         lat.set_launch(*launch)
