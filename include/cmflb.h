@@ -320,11 +320,12 @@ int cmf_ensemble_destroy(cmf_ensemble *ens);
 int cmf_ensemble_info(cmf_ensemble *ens, int32_t *n_replicas,
                       int64_t *total_sites, int64_t *n_tiles);
 
-/* Tile shape of the ensemble step kernel: a tile is spt x 256 consecutive
- * sites of one replica (spt9 for D2Q9 replicas, spt3d for D3Q19 and D3Q27
- * replicas; one workgroup of 256 threads per tile, each thread spt sites).
- * Defaults 3 and 1 (environment variables CMF_ENSEMBLE_SPT9 and
- * CMF_ENSEMBLE_SPT27 override them at creation). */
+/* Tile shape of the ensemble step kernel: one workgroup of 256 threads per
+ * tile, each thread up to spt sites (spt9 for D2Q9 replicas, spt3d for
+ * D3Q19 and D3Q27 replicas); a tile holds as many whole rows of its replica
+ * as fit in spt x 256 sites, or spt x 256 sites of a longer row.  Defaults
+ * 3 and 1 (environment variables CMF_ENSEMBLE_SPT9 and CMF_ENSEMBLE_SPT27
+ * override them at creation). */
 typedef struct {
   int32_t spt9;
   int32_t spt3d;

@@ -1325,7 +1325,7 @@ struct cmf_ensemble {
     cmf_desc desc;
     int64_t N = 0;
     int64_t offset = 0;  // elements
-    int tile0 = 0, ntiles = 0, spt = 1;
+    int tile0 = 0, ntiles = 0, spt = 1, tsites = 0;
     ConvParams cp;
   };
   int n = 0;
@@ -1370,6 +1370,7 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
   p.tile0 = rp.tile0;
   p.ntiles = rp.ntiles;
   p.spt = rp.spt;
+  p.tsites = rp.tsites;
   p.noise = d.kT > 0.0 ? 1 : 0;
   p.offset = rp.offset;
   p.key0 = (uint32_t)d.seed;
@@ -1444,22 +1445,25 @@ void *ens_replica_buffer(cmf_ensemble *E, int index) {
   return (char *)E->arena[E->parity] + E->reps[index].offset * storage_bytes(E->storage);
 }
 
-// Tile the replicas with spt9 (D2Q9) / spt3d (D3Q19, D3Q27) x kEnsembleBlock
-// sites per tile: 3-D replicas first, then D2Q9, each in creation order.
-// Uploads the tile map and the replica records, grows the tile map and the
-// partial-sum buffers when needed and drops captured graphs.  The stream
-// must be idle.
+// Tile the replicas, 3-D replicas first, then D2Q9, each in creation order:
+// a tile of a replica takes as many whole rows as fit in spt x
+// kEnsembleBlock sites, spt = spt9 (D2Q9) or spt3d (D3Q19, D3Q27), or that
+// many sites when one row is longer.  Uploads the tile map and the replica
+// records, grows the tile map and the partial-sum buffers when needed and
+// drops captured graphs.  The stream must be idle.
 int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
   std::vector<int32_t> tile_rep;
-  std::vector<int> tile0(E->n), ntl(E->n), spt(E->n);
+  std::vector<int> tile0(E->n), ntl(E->n), spt(E->n), tsites(E->n);
   for (int pass = 0; pass < 2; ++pass)
     for (int r = 0; r < E->n; ++r) {
       const int q = E->reps[r].desc.q;
       if ((pass == 0) != (q != 9)) continue;
       tile0[r] = (int)tile_rep.size();
       spt[r] = q == 9 ? spt9 : spt3d;
-      const int64_t tsites = (int64_t)spt[r] * kEnsembleBlock;
-      const int64_t n = (E->reps[r].N + tsites - 1) / tsites;
+      const int64_t lanes = (int64_t)spt[r] * kEnsembleBlock;
+      const int64_t nx = E->reps[r].desc.nx;
+      tsites[r] = (int)(nx <= lanes ? lanes / nx * nx : lanes);
+      const int64_t n = (E->reps[r].N + tsites[r] - 1) / tsites[r];
       if ((int64_t)tile_rep.size() + n >= ((int64_t)1 << 31))
         return fail(CMF_EINVAL, "ensemble has too many tiles");
       ntl[r] = (int)n;
@@ -1485,6 +1489,7 @@ int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
     E->reps[r].tile0 = tile0[r];
     E->reps[r].ntiles = ntl[r];
     E->reps[r].spt = spt[r];
+    E->reps[r].tsites = tsites[r];
   }
   E->ntiles = nt;
   E->spt9 = spt9;

@@ -44,7 +44,8 @@ struct ReplicaParams {
   int32_t nsites, tile0, ntiles, noise;
   int64_t offset;  // element offset of the replica's populations in an arena
   uint32_t key0, key1, replica;
-  int32_t spt;  // sites per thread: a tile is spt x kEnsembleBlock sites
+  int32_t spt;     // sites per thread: a tile has at most spt x kEnsembleBlock sites
+  int32_t tsites;  // sites per tile: the whole rows that fit, or spt x kEnsembleBlock
   R rho0;
   R amp[27];
   R amp1;

@@ -472,8 +472,8 @@ __device__ __forceinline__ const T *at_byte(const T *base, uint32_t boff) {
 // the per-lane 64-bit address arithmetic.
 // NT_C0: non-temporal loads for the populations with c_x = 0, only when
 // every population row is a whole number of cache lines (then tiles, which
-// start at multiples of 256 sites of a replica or row, never share a line
-// of such a row).
+// start at a row or at a multiple of 256 sites of a row, never share a
+// line of such a row).
 template <class L, typename S, typename R, bool LANE_ROWS, bool NT_C0 = false>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
                                           const float *scale, int nx, int ny,
@@ -1061,9 +1061,12 @@ __global__ __launch_bounds__(256) void k_vel_hist(const ConvParams cp,
 // ---------------------------------------------------------------------------
 // batched ensemble: one launch per step over the tiles of every replica
 // ---------------------------------------------------------------------------
-// A tile is spt x kEnsembleBlock consecutive sites (x fastest) of one
-// replica, so every lane of a workgroup is busy whatever the box edges; the
-// replica, and with it the lattice type, is uniform per workgroup.
+// A tile is a run of consecutive sites (x fastest) of one replica: as many
+// whole lattice rows as fit in spt x kEnsembleBlock sites, or that many
+// sites of a longer row.  Whole rows keep every cache line of a row, and of
+// the population rows stored around it, inside one workgroup; the lanes
+// beyond the tile's rows idle.  The replica, and with it the lattice type,
+// is uniform per workgroup.
 // Replicas are listed 3-D first (heavier tiles dispatched first).
 template <class L, typename S, typename R, bool GENERAL, bool NT>
 __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
@@ -1109,21 +1112,23 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
   Acc acc;
 #pragma unroll
   for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
-  const int64_t s0 = (int64_t)(tile - p.tile0) * p.spt * kEnsembleBlock + threadIdx.x;
+  const int64_t t0 = (int64_t)(tile - p.tile0) * p.tsites;
+  const int64_t s0 = t0 + threadIdx.x;
+  const int64_t end = t0 + p.tsites < p.nsites ? t0 + p.tsites : p.nsites;
   if (p.q == 27) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < p.nsites) ensemble_site<D3Q27, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q27, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   } else if (p.q == 19) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < p.nsites) ensemble_site<D3Q19, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q19, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   } else {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < p.nsites) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
     }
   }
   block_store_acc_shuffle(acc, partials + (int64_t)tile * kPartStride);
