@@ -1358,6 +1358,17 @@ struct cmf_ensemble {
 
 namespace {
 
+// multiplier and shifts of the exact division by d >= 1 that
+// udiv_invariant applies (Granlund and Montgomery, PLDI 1994, Fig. 4.1):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0)
+void invariant_divisor(uint32_t d, uint32_t *m, uint32_t *sh) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  *m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  *sh = (uint32_t)(l < 1 ? l : 1) | ((uint32_t)(l > 1 ? l - 1 : 0) << 8);
+}
+
 template <typename R>
 void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble::Rep &rp,
                   ReplicaParams<R> &p) {
@@ -1371,6 +1382,8 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
   p.ntiles = rp.ntiles;
   p.spt = rp.spt;
   p.tsites = rp.tsites;
+  invariant_divisor((uint32_t)d.nx, &p.div_nx, &p.sh_nx);
+  invariant_divisor((uint32_t)d.ny, &p.div_ny, &p.sh_ny);
   p.noise = d.kT > 0.0 ? 1 : 0;
   p.offset = rp.offset;
   p.key0 = (uint32_t)d.seed;

@@ -46,6 +46,9 @@ struct ReplicaParams {
   uint32_t key0, key1, replica;
   int32_t spt;     // sites per thread: a tile has at most spt x kEnsembleBlock sites
   int32_t tsites;  // sites per tile: the whole rows that fit, or spt x kEnsembleBlock
+  // exact division of a site index by nx and of a row index by ny with a
+  // multiplier m and shifts s1 | s2 << 8 (see udiv_invariant)
+  uint32_t div_nx, div_ny, sh_nx, sh_ny;
   R rho0;
   R amp[27];
   R amp1;

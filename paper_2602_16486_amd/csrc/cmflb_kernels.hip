@@ -1068,6 +1068,16 @@ __global__ __launch_bounds__(256) void k_vel_hist(const ConvParams cp,
 // beyond the tile's rows idle.  The replica, and with it the lattice type,
 // is uniform per workgroup.
 // Replicas are listed 3-D first (heavier tiles dispatched first).
+// n / d for any 32-bit n by a multiply-high and two shifts, with m and
+// s1 | s2 << 8 precomputed for the divisor d (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", PLDI 1994,
+// Fig. 4.1): t = mulhi(m, n), q = (t + ((n - t) >> s1)) >> s2, in place of
+// a generic 32-bit division, which forms and corrects a reciprocal per lane.
+__device__ __forceinline__ uint32_t udiv_invariant(uint32_t n, uint32_t m, uint32_t sh) {
+  const uint32_t t = __umulhi(m, n);
+  return (t + ((n - t) >> (sh & 255u))) >> (sh >> 8);
+}
+
 template <class L, typename S, typename R, bool GENERAL, bool NT>
 __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
                                               S *__restrict__ dst,
@@ -1076,10 +1086,11 @@ __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
                                               Acc &acc) {
   const uint32_t nx = (uint32_t)p.nx, ny = (uint32_t)p.ny;
   const uint32_t us = (uint32_t)s;
-  const uint32_t row = us / nx;
+  const uint32_t row = udiv_invariant(us, p.div_nx, p.sh_nx);
   const int x = (int)(us - row * nx);
-  const int y = (int)(row % ny);
-  const int z = (int)(row / ny);
+  const uint32_t zr = udiv_invariant(row, p.div_ny, p.sh_ny);
+  const int y = (int)(row - zr * ny);
+  const int z = (int)zr;
   R d[L::Q];
   load_site<L, S, R, true, NT>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
   collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);

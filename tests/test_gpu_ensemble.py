@@ -261,3 +261,34 @@ def test_invalid_fields_and_cap_leave_the_ensemble_unchanged():
         for k in range(2):
             assert np.array_equal(ens.get_populations(k), before[k])
             assert np.array_equal(ens.stats(k)[:, 0], np.arange(2))
+
+
+def test_degenerate_replicas_match_standalone_lattices():
+    """Replicas with edges of 1 and 2 sites (exact divisions by 1 and 2 in the
+    tile-to-site mapping, rows shorter than a wave) and one row longer than a
+    tile, next to ordinary ones: bit-identical to standalone lattices."""
+    reps = [
+        {"q": 9, "shape": (1, 7), "kT": 1e-4, "tau": 0.8, "seed": 21},
+        {"q": 9, "shape": (5, 1), "kT": 1e-4, "tau": 0.6, "seed": 22},
+        {"q": 9, "shape": (1, 1), "kT": 1e-4, "tau": 0.9, "seed": 23},
+        {"q": 27, "shape": (1, 3, 2), "kT": 2e-4, "tau": 0.7, "seed": 24},
+        {"q": 27, "shape": (2, 1, 1), "kT": 2e-4, "tau": 0.7, "seed": 25},
+        {"q": 19, "shape": (1, 1, 4), "kT": 2e-4, "tau": 0.7, "seed": 26},
+        {"q": 9, "shape": (1100, 3), "kT": 1e-5, "tau": 1.5, "seed": 27},
+        {"q": 27, "shape": (9, 7, 5), "kT": 1e-4, "tau": 0.8, "seed": 28},
+    ]
+    for k, r in enumerate(reps):
+        r["replica"] = k
+    steps = 36
+    states = [_state(r, 300 + k) for k, r in enumerate(reps)]
+    with Ensemble(reps, storage="f32") as ens:
+        for k, f in enumerate(states):
+            ens.set_populations(k, f)
+        ens.step(steps)
+        got = [ens.get_populations(k) for k in range(len(reps))]
+    for k, r in enumerate(reps):
+        kw = {key: r[key] for key in ("kT", "tau", "seed", "replica")}
+        with Lattice(r["q"], r["shape"], storage="f32", **kw) as lat:
+            lat.set_populations(states[k])
+            lat.step(steps)
+            assert np.array_equal(got[k], lat.get_populations()), f"replica {k} {r['shape']}"
