@@ -1,5 +1,5 @@
 """Whole runs at sizes the oracle finishes in seconds: D2Q9 64^2 in full
-(2000 steps) and a D3Q27 48^3 run standing in for the 256^3 benchmark box
+(2000 steps) and a D3Q27 64^3 run standing in for the 256^3 benchmark box
 (FP32 / FP16 / BF16 storage against the FP64 oracle).  Needs an MI355X."""
 import math
 
@@ -53,9 +53,9 @@ def test_d2q9_64_full_run(storage, d2q9_64_oracle):
 
 
 @pytest.fixture(scope="module")
-def d3q27_48_oracle():
-    q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
-    n = 48 ** 3
+def d3q27_64_oracle():
+    q, shape, kT, tau, steps, every = 27, (64, 64, 64), 1e-4, 0.8, 120, 20
+    n = 64 ** 3
     f = O.init_equilibrium(q, n, 1.0)
     lam = O.paper_lambda(q, 1 / tau)
     sa = spectra.ShellAverager(shape, 16)
@@ -67,12 +67,12 @@ def d3q27_48_oracle():
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_d3q27_48_storage_against_oracle(storage, d3q27_48_oracle):
-    """48^3 subrun of the 256^3 storage comparison: <u^2> (averaged over the
+def test_d3q27_64_storage_against_oracle(storage, d3q27_64_oracle):
+    """64^3 subrun of the 256^3 storage comparison: <u^2> (averaged over the
     run) within 1% of the FP64 oracle for every storage type, and the
     structure factor shells within 2% (FP32 within 1e-4)."""
-    q, shape, kT, tau, steps, every = 27, (48, 48, 48), 1e-4, 0.8, 120, 20
-    st_ref, sk_ref = d3q27_48_oracle
+    q, shape, kT, tau, steps, every = 27, (64, 64, 64), 1e-4, 0.8, 120, 20
+    st_ref, sk_ref = d3q27_64_oracle
     with Lattice(q, shape, storage=storage, tau=tau, kT=kT, seed=1) as lat:
         lat.sk_reset(16)
         for _ in range(steps // every):
@@ -80,15 +80,15 @@ def test_d3q27_48_storage_against_oracle(storage, d3q27_48_oracle):
             lat.sk_accumulate()
         st = lat.stats()
         sk, _ = lat.sk_shells()
-    n = 48 ** 3
+    n = 64 ** 3
     u2 = st[:, 8:11].sum(axis=1) / n
     u2_ref = st_ref[:, 8:11].sum(axis=1) / n
     rel = abs(u2[20:].mean() / u2_ref[20:].mean() - 1)
     # step 0 is the rest state (u = 0 on both sides)
     per_step = np.abs(u2[1:] / u2_ref[1:] - 1).max()
-    print(f"D3Q27 48^3 {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
+    print(f"D3Q27 64^3 {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
     assert rel < (1e-4 if storage == "f32" else 1e-2)
     sel = sk_ref[:, 1] > 0
     srel = np.abs(sk[sel, 2:5] / sk_ref[sel, 2:5] - 1).max()
-    print(f"D3Q27 48^3 {storage}: S(k) worst shell rel diff {srel:.2e}")
+    print(f"D3Q27 64^3 {storage}: S(k) worst shell rel diff {srel:.2e}")
     assert srel < (1e-4 if storage == "f32" else 2e-2)
