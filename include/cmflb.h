@@ -3,11 +3,12 @@
  * fused stream-and-collide step of the fluctuating orthogonal-central-moment
  * lattice Boltzmann method (De Rosis & Zhou, "A fluctuating lattice
  * Boltzmann formulation based on orthogonal central moments",
- * arXiv 2602.16486), for the D2Q9 and D3Q27 lattices on periodic boxes.
+ * arXiv 2602.16486), for the D2Q9, D3Q27 and D3Q19 lattices on periodic
+ * boxes.
  *
  * One time step is the paper's per-site algorithm (Sec. 2.2, "Algorithm of
  * computation"): density and velocity (eq. macro), standard normals for the
- * non-conserved modes, central moments k = T(u) f (Sec. 2.2/2.3), the
+ * non-conserved modes, central moments k = T(u) f (Sec. 2.2, 2.3, 2.4), the
  * collision k* = (I - Lambda) k + Lambda k_eq + I~ phi eta (eq. cm_collision)
  * with phi from eq. phi_general, the back transformation f* = T(u)^-1 k*,
  * and the streaming f_i(x + c_i, t + 1) = f*_i(x, t) (eq. streaming).
@@ -15,16 +16,18 @@
  * Conventions shared by every entry point:
  *  - Site order is x fastest: s = x + nx * (y + ny * z); nz = 1 for D2Q9.
  *  - Population order is the paper's velocity order (Sec. 2.2 for D2Q9,
- *    Sec. 2.3 for D3Q27).  "Populations" at the ABI are the pre-collision
- *    populations f_i(x, t) of the current step t, in FP64, laid out q x N
- *    (population-major).
+ *    Sec. 2.3 for D3Q27; D3Q19, whose order Sec. 2.4 does not give, uses
+ *    the D3Q27 order without the eight corners).  "Populations" at the ABI
+ *    are the pre-collision populations f_i(x, t) of the current step t, in
+ *    FP64, laid out q x N (population-major).
  *  - Noise: eta of mode v at site s and step t comes from Philox4x32-10
  *    (Salmon et al., SC'11) with key (seed low word, seed high word) and
- *    counter (s, t, replica, block); normal n = v - 3 (D2Q9) or v - 4 (D3Q27),
- *    pair p = n / 2 uses block p / 2 and words 2 (p mod 2), 2 (p mod 2) + 1 as
- *    (a, b); u1 = ((a >> 8) + 1) 2^-24, u2 = (b >> 8) 2^-24; the pair is
- *    r cos(2 pi u2), r sin(2 pi u2) with r = sqrt(-2 ln u1) (even n takes the
- *    cosine).  Results do not depend on tiling or launch shape.
+ *    counter (s, t, replica, block); normal n = v - 3 (D2Q9) or v - 4
+ *    (D3Q19, D3Q27), pair p = n / 2 uses block p / 2 and words 2 (p mod 2),
+ *    2 (p mod 2) + 1 as (a, b); u1 = ((a >> 8) + 1) 2^-24,
+ *    u2 = (b >> 8) 2^-24; the pair is r cos(2 pi u2), r sin(2 pi u2) with
+ *    r = sqrt(-2 ln u1) (even n takes the cosine).  Results do not depend
+ *    on tiling or launch shape.
  *  - Every function returns CMF_OK (0) or a negative status; the message of
  *    the last failure on the calling thread is cmf_last_error().  No
  *    exception crosses the ABI.
@@ -71,7 +74,7 @@ enum {
 #define CMF_FLAG_NO_STATS 2u   /* skip the per-step statistics finalize */
 
 typedef struct {
-  int32_t q;         /* 9 (D2Q9) or 27 (D3Q27) */
+  int32_t q;         /* 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27) */
   int32_t nx, ny, nz;/* box edges, >= 1; nz must be 1 for D2Q9 */
   int32_t storage;   /* CMF_STORE_* */
   uint32_t flags;    /* CMF_FLAG_* */
@@ -293,8 +296,8 @@ int cmf_sk_accumulate(cmf_lattice *lat);
 int cmf_sk_shells(cmf_lattice *lat, double *out, int64_t *nsamples);
 
 /* ---- batched ensembles ------------------------------------------------
- * Many independent replicas (D2Q9 and D3Q27 mixed; uneven boxes; each with
- * its own tau / rates, kT, rho0, seed and replica number) advanced together
+ * Many independent replicas (D2Q9, D3Q19 and D3Q27 mixed; uneven boxes;
+ * each with its own tau / rates, kT, rho0, seed and replica number) advanced together
  * by ONE fused-step launch per step that covers the tiles of every replica,
  * followed by a per-replica statistics reduction; runs of steps are
  * replayed from captured HIP graphs unless CMF_FLAG_NO_GRAPH.  Each replica

@@ -1,6 +1,6 @@
 """MI355X (gfx950) implementation of the fused stream-and-collide step of the
 fluctuating orthogonal-central-moment lattice Boltzmann method (De Rosis &
-Zhou, arXiv 2602.16486) for D2Q9 and D3Q27.
+Zhou, arXiv 2602.16486) for D2Q9, D3Q19 and D3Q27.
 
 The compute path is the HIP library ``libcmflb.so`` (C ABI in
 ``include/cmflb.h``); this package is its ctypes binding.  Importing the
