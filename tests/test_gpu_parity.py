@@ -305,6 +305,27 @@ def test_nonfinite_is_reported():
         assert exc.value.code == _lib.CMF_ENONFINITE
 
 
+def test_empty_calls_are_no_ops():
+    """Zero steps, an empty site list, a statistics read with no new step and
+    a zero-step profile change nothing; the next real step is step 0's
+    successor as if they had not happened."""
+    import ctypes
+    shape = (20, 9, 7)
+    with Lattice(27, shape, storage="f32", kT=1e-4, seed=6) as lat, \
+            Lattice(27, shape, storage="f32", kT=1e-4, seed=6) as ref:
+        lat.step(0)
+        assert lat.step_index == 0
+        assert lat.gather_sites(np.zeros(0, dtype=np.int64)).shape == (0, 27)
+        assert lat.stats().shape == (0, 12)
+        ms = ctypes.c_double(1.0)
+        assert lat._lib.cmf_profile_steps(lat._h, 0, ctypes.byref(ms)) == _lib.CMF_OK and ms.value == 0.0
+        lat.step(5)
+        ref.step(5)
+        assert lat.step_index == 5
+        assert np.array_equal(lat.get_populations(), ref.get_populations())
+        assert np.array_equal(lat.stats(), ref.stats())
+
+
 def test_invalid_fields_and_cap_leave_the_lattice_unchanged():
     """cmf_init_equilibrium rejects a non-positive density and a non-finite
     velocity, and cmf_stats a negative cap, with CMF_EINVAL before touching
