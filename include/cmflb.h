@@ -37,7 +37,12 @@
  *  - Steps are enqueued asynchronously on the HIP stream given at creation
  *    (NULL: the lattice creates a stream of its own, default priority, and
  *    destroys it with the lattice); every call that returns host data
- *    synchronises that stream first.
+ *    synchronises that stream first.  A lattice lives on the device that is
+ *    current when it is created; a stream passed in must belong to it.
+ *  - Threads: different lattices and ensembles may be used from different
+ *    host threads at the same time (graph capture is thread-local, the
+ *    process-wide launch-shape cache is locked); one lattice or ensemble
+ *    must not be used by two threads at once.
  */
 #ifndef CMFLB_H
 #define CMFLB_H
