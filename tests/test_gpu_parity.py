@@ -305,6 +305,41 @@ def test_nonfinite_is_reported():
         assert exc.value.code == _lib.CMF_ENONFINITE
 
 
+def test_tune_cache_file_round_trip(tmp_path):
+    """CMFLB_TUNE_CACHE: an autotuned launch shape is appended to the file
+    and a later process creating the same lattice starts with it; a file
+    with malformed lines is read up to the first bad line and never fails a
+    creation."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    code = ("import sys, json; sys.path.insert(0, %r)\n"
+            "from paper_2602_16486_amd import Lattice\n"
+            "with Lattice(27, (40, 12, 10), storage='f32', kT=1e-4) as lat:\n"
+            "    first = list(lat.launch)\n"
+            "    if sys.argv[1] == 'tune':\n"
+            "        lat.autotune(steps_per_trial=2)\n"
+            "    print(json.dumps([first, list(lat.launch)]))\n" % root)
+    env = dict(os.environ, CMFLB_TUNE_CACHE=str(cache))
+
+    def run(mode):
+        out = subprocess.run([sys.executable, "-c", code, mode], env=env, capture_output=True,
+                             text=True, timeout=120)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+    _, tuned = run("tune")
+    lines = cache.read_text().split("\n")
+    assert any(line.startswith("dev") and line.split()[1:3] == [str(v) for v in tuned] for line in lines)
+    first, _ = run("plain")
+    assert first == tuned
+    cache.write_text("this is not a cache line\n")
+    first, _ = run("plain")
+    assert first[0] in (64, 128, 192, 256) and first[1] >= 1
+
+
 def test_empty_calls_are_no_ops():
     """Zero steps, an empty site list, a statistics read with no new step and
     a zero-step profile change nothing; the next real step is step 0's
