@@ -72,6 +72,10 @@ def test_null_arguments_are_rejected():
     assert lib.cmf_ensemble_get_tiles(None, None) == _lib.CMF_EINVAL
     assert lib.cmf_ensemble_set_tiles(None, 3, 1) == _lib.CMF_EINVAL
     assert lib.cmf_ensemble_autotune(None, 2, None, 0, None) == _lib.CMF_EINVAL
+    ms = ctypes.c_double()
+    assert lib.cmf_stream_copy(0, 1, ctypes.byref(ms)) == _lib.CMF_EINVAL
+    assert lib.cmf_stream_copy(1 << 20, 0, ctypes.byref(ms)) == _lib.CMF_EINVAL
+    assert lib.cmf_stream_copy(1 << 20, 1, None) == _lib.CMF_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -591,6 +591,42 @@ def test_external_buffers_from_torch():
         Lattice(q, shape, storage="f32", external=(host.ctypes.data, nbytes))
 
 
+@pytest.mark.parametrize("q,shape", [(9, (33, 17)), (19, (20, 12, 9)), (27, (20, 12, 9))])
+def test_sample_macro_into_torch_buffers(q, shape):
+    """cmf_sample_macro writes rho (N floats) and u (3 N floats, u_x block
+    first) of the current state into caller device buffers (torch tensors):
+    the FP64 values of cmf_get_macro rounded to FP32, exactly; either buffer
+    may be NULL, and nothing beyond the N and 3 N floats is written."""
+    import torch
+    n = W.n_sites(shape)
+    dims = 2 if q == 9 else 3
+    rho, u = W.random_macro(shape, 51, umax=0.03, dims=dims)
+    f = O.init_equilibrium(q, n, rho=rho, u=u) + W.perturbation(q, n, 52, 5e-4)
+    r_t = torch.full((n + 64,), -7.0, dtype=torch.float32, device="cuda")
+    u_t = torch.full((3 * n + 64,), -7.0, dtype=torch.float32, device="cuda")
+    r2_t = torch.full((n,), -7.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    with Lattice(q, shape, storage="f32", tau=0.7, kT=1e-4, seed=53) as lat:
+        lat.set_populations(f)
+        lat.step(5)
+        rho64, u64 = lat.macroscopic()
+        lat.sample_macro(r_t.data_ptr(), u_t.data_ptr())
+        lat.sample_macro(r2_t.data_ptr(), 0)
+        lat.synchronize()
+    got_r, got_u = r_t.cpu().numpy(), u_t.cpu().numpy()
+    assert np.array_equal(got_r[:n], rho64.astype(np.float32))
+    assert np.array_equal(got_u[:3 * n].reshape(3, n), u64.astype(np.float32))
+    assert np.all(got_r[n:] == -7.0) and np.all(got_u[3 * n:] == -7.0)
+    assert np.array_equal(r2_t.cpu().numpy(), got_r[:n])
+
+
+def test_stream_copy_diagnostic():
+    """cmf_stream_copy times a plain copy of the given size and returns the
+    fastest of `reps` runs."""
+    ms = _lib.stream_copy(64 << 20, reps=3)
+    assert 0.0 < ms < 100.0
+
+
 @pytest.mark.parametrize("q,shape", [(9, (1, 1)), (9, (1, 5)), (9, (7, 1)), (9, (2, 2)),
                                      (27, (1, 1, 1)), (27, (2, 1, 3)), (27, (1, 4, 1)),
                                      (19, (1, 1, 1)), (19, (3, 1, 2))])
