@@ -69,6 +69,22 @@ def measured_traffic(launch):
     return c["traffic_bytes_per_launch"]
 
 
+REPEATS = 5  # further timed runs of `steps` steps, for the median
+
+
+def time_steps(lat, steps, stream, torch):
+    """Wall clock of `steps` steps on the lattice's stream (ms per step),
+    bracketed by device synchronisations."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    lat.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
 def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
     from paper_2602_16486_amd import Lattice
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
@@ -78,26 +94,22 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
             lat.autotune(steps_per_trial=10)  # untimed; state restored
         launch = lat.launch
         lat.step(warmup)
-        torch.cuda.synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        lat.step(steps)
-        end.record(stream)
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(end)
+        # the headline: exactly `steps` steps after the warm-up
+        ms_step = time_steps(lat, steps, stream, torch)
+        repeats = [time_steps(lat, steps, stream, torch) for _ in range(REPEATS)]
         # live per-kernel duration of the fused step (HIP events around each
         # launch on the lattice's stream), same state, direct launches
         kprof = 20
         kernel_ms = lat.profile_steps(kprof) / kprof
         st = lat.stats()
-    ms_step = ms / steps
     glups = n / (ms_step * 1e-3) / 1e9
     # equipartition over the recorded steps after the first 30 (warm-up)
     u2 = st[30:, 8:11].sum(axis=1) / (3 * n)
     return {
         "launch": launch,
         "ms_per_step": ms_step,
+        "repeat_ms_per_step": repeats,
+        "median_ms_per_step": float(sorted(repeats + [ms_step])[(REPEATS + 1) // 2]),
         "glups": glups,
         "kernel_ms": kernel_ms,
         "kernel_gbs": bytes_per_site(storage, q) * n / (kernel_ms * 1e-3) / 1e9,
@@ -170,30 +182,37 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
 
 
 def cpu_baseline():
-    """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 160 steps
+    """The FP64 oracle, as it is, on the host cores: D3Q27 64^3 for 100 steps
     from rest (same parameters as the GPU workload) with the dense T(u) + LU
-    reconstruction on every thread (the reported value), plus the oracle's
-    second reconstruction form (M^-1 N(-u), 64^3 x 80 steps) and both forms
-    on one core (32^3 x 10 steps)."""
+    reconstruction on every thread (the reported value), plus D2Q9 1024^2
+    for 200 steps (the D2Q9 workload's box), the oracle's second
+    reconstruction form (M^-1 N(-u), 64^3 x 40 steps) and both forms on one
+    core (32^3 x 10 steps)."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
 
-    def timed(shape, steps, method, nthreads):
-        n = shape[0] * shape[1] * shape[2]
-        f = O.init_equilibrium(Q, n, rho0=RHO0)
+    def timed(shape, steps, method, nthreads, q=Q):
+        n = 1
+        for e in shape:
+            n *= e
+        f = O.init_equilibrium(q, n, rho0=RHO0)
         t0 = time.perf_counter()
-        O.run(Q, shape, f, KT, O.paper_lambda(Q, 1 / TAU), SEED, 0, 0, steps, method=method,
+        O.run(q, shape, f, KT, O.paper_lambda(q, 1 / TAU), SEED, 0, 0, steps, method=method,
               nthreads=nthreads)
         dt = time.perf_counter() - t0
         return n * steps / dt, dt
 
-    rate, dt = timed((64, 64, 64), 160, 0, threads)
-    shift, _ = timed((64, 64, 64), 80, 1, threads)
+    rate, dt = timed((64, 64, 64), 100, 0, threads)
+    d2q9, dt9 = timed((1024, 1024), 200, 0, threads, q=9)
+    shift, _ = timed((64, 64, 64), 40, 1, threads)
     one_lu, _ = timed((32, 32, 32), 10, 0, 1)
     one_shift, _ = timed((32, 32, 32), 10, 1, 1)
     return {"value": rate / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"D3Q27 64^3 x 160 steps from rest (rho0=1, tau=0.8, kT=1e-4, seed 1), "
+            "sample": f"D3Q27 64^3 x 100 steps from rest (rho0=1, tau=0.8, kT=1e-4, seed 1), "
                       f"FP64 dense T(u) + LU, {dt:.1f} s",
+            "d2q9_1024": {"value": d2q9 / 1e9, "unit": "GLUPS",
+                          "sample": f"D2Q9 1024^2 x 200 steps from rest, same parameters, FP64 "
+                                    f"dense T(u) + LU, {dt9:.1f} s"},
             "forms_mlups": {"dense_lu": rate / 1e6, "shift_reconstruction": shift / 1e6,
                             "dense_lu_one_core": one_lu / 1e6,
                             "shift_reconstruction_one_core": one_shift / 1e6}}
@@ -215,8 +234,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    if args.warmup < 32:
-        args.warmup = 32  # the first graph capture happens inside the warm-up
+    if args.steps < 1 or args.warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
 
     import numpy as np
     import torch
@@ -282,6 +302,18 @@ def main():
             "lattice": "D3Q27", "box": list(SHAPE), "storage": "f32",
             "bytes_per_site_step": bytes_per_site("f32"),
             "launch": list(main_run["launch"]),
+            # environment variables that select launch or tile shapes (never results)
+            "env": {k: os.environ[k] for k in ("CMFLB_TUNE_CACHE", "CMF_ENSEMBLE_SPT9",
+                                               "CMF_ENSEMBLE_SPT27") if k in os.environ},
+        },
+        "timing": {
+            "protocol": f"{args.warmup} warm-up steps, then {args.steps} timed steps (the value); "
+                        f"then {REPEATS} more timed runs of {args.steps} steps; CUDA/HIP events on "
+                        f"the lattice's stream around cmf_step (32-step graph replays and direct "
+                        f"steps, statistics reductions overlapped on a second stream)",
+            "repeat_ms_per_step": main_run["repeat_ms_per_step"],
+            "median_ms_per_step": main_run["median_ms_per_step"],
+            "median_glups": n / (main_run["median_ms_per_step"] * 1e-3) / 1e9,
         },
         "roofline": {
             "bound": "hbm",

@@ -20,9 +20,13 @@
  *    the D3Q27 order without the eight corners).  "Populations" at the ABI
  *    are the pre-collision populations f_i(x, t) of the current step t, in
  *    FP64, laid out q x N (population-major).
- *  - Noise: eta of mode v at site s and step t comes from Philox4x32-10
- *    (Salmon et al., SC'11) with key (seed low word, seed high word) and
- *    counter (s, t, replica, block); normal n = v - 3 (D2Q9) or v - 4
+ *  - Noise: the paper asks for independent standard normal variables
+ *    (Sec. 2.1, eq. Xi_pop); eta of mode v at site s and step t comes from
+ *    Philox4x32-10 (Salmon et al., SC'11) with key (seed low word, seed high
+ *    word) and counter (s, t mod 2^32, replica, block + 256 floor(t / 2^32))
+ *    -- (s, t, replica, block) for t < 2^32; the counters of all steps below
+ *    2^56 are distinct, and no call accepts a step beyond that (about 2
+ *    million years of steps at one per microsecond); normal n = v - 3 (D2Q9) or v - 4
  *    (D3Q19, D3Q27), pair p = n / 2 uses block p / 2 and words 2 (p mod 2),
  *    2 (p mod 2) + 1 as (a, b); u1 = ((a >> 8) + 1) 2^-24,
  *    u2 = (b >> 8) 2^-24; the pair is r cos(2 pi u2), r sin(2 pi u2) with
@@ -161,13 +165,17 @@ int cmf_destroy(cmf_lattice *lat);
  * finite or a velocity component is not finite. */
 int cmf_init_equilibrium(cmf_lattice *lat, const double *rho, const double *u);
 
-/* Overwrite the pre-collision populations f_i(x, t) of the current step with
- * q x N host doubles (canonical layout).  The step counter is unchanged.
- * Synchronous. */
+/* Overwrite the pre-collision populations f_i(x, t) of the current step
+ * (the f of eq. lbe before its collision, Sec. 2.1) with q x N host doubles
+ * (canonical layout).  The step counter is unchanged.  Allocates a
+ * temporary device buffer of q N doubles.  Synchronous.  Errors: CMF_EINVAL
+ * (NULL argument), CMF_ENOMEM, CMF_EHIP. */
 int cmf_set_populations(cmf_lattice *lat, const double *f);
 
-/* Copy the pre-collision populations f_i(x, t) of the current step into
- * q x N host doubles (canonical layout).  Synchronous. */
+/* Copy the pre-collision populations f_i(x, t) of the current step (the f
+ * of eq. lbe before its collision, Sec. 2.1) into q x N host doubles
+ * (canonical layout).  Allocates a temporary device buffer of q N doubles.
+ * Synchronous.  Errors: CMF_EINVAL (NULL argument), CMF_ENOMEM, CMF_EHIP. */
 int cmf_get_populations(cmf_lattice *lat, double *f);
 
 /* Pre-collision populations of the current step at `n` sites: out[k*q + i]
@@ -175,10 +183,16 @@ int cmf_get_populations(cmf_lattice *lat, double *f);
 int cmf_gather_sites(cmf_lattice *lat, const int64_t *sites, int64_t n,
                      double *out);
 
-/* Enqueue `nsteps` fused steps (plus the statistics finalize of each step
- * unless CMF_FLAG_NO_STATS) on the lattice's stream.  Runs of steps are
+/* Enqueue `nsteps` time steps on the lattice's stream.  One step is the
+ * paper's per-site algorithm (Sec. 2.2, "Algorithm of computation"; the
+ * D3Q27 and D3Q19 forms of Sec. 2.3 and 2.4): density and velocity (eq.
+ * macro), normals, central moments, the collision of eq. cm_collision with
+ * phi of eq. phi_general, f* = T(u)^-1 k*, and the streaming of eq.
+ * streaming on the periodic box; plus, unless CMF_FLAG_NO_STATS, the
+ * statistics row of the step (see cmf_stats).  Runs of 32 steps are
  * replayed from captured HIP graphs unless CMF_FLAG_NO_GRAPH.
- * Asynchronous; nsteps >= 0. */
+ * Asynchronous; nsteps >= 0.  Errors: CMF_EINVAL (NULL lattice,
+ * nsteps < 0), CMF_EHIP (launch or graph capture failed). */
 int cmf_step(cmf_lattice *lat, int64_t nsteps);
 
 /* Diagnostic timing: enqueue `nsteps` steps as direct launches (no graph)
@@ -227,7 +241,18 @@ int cmf_synchronize(cmf_lattice *lat);
 /* Index of the next step to be computed (synchronises). */
 int cmf_get_step(cmf_lattice *lat, int64_t *step);
 
-/* Statistics rows of the steps completed since the previous call (or since
+/* Set the index of the next step to be computed, e.g. to resume a run from
+ * saved populations (cmf_get_populations + cmf_get_step, later
+ * cmf_set_populations + cmf_set_step continue with the same noise).  Rows
+ * of earlier steps are no longer returned by cmf_stats.  Synchronous.
+ * Errors: CMF_EINVAL (NULL lattice, step outside [0, 2^56)), CMF_EHIP. */
+int cmf_set_step(cmf_lattice *lat, int64_t step);
+
+/* The per-step spatial sums behind the diagnostics of Sec. 3 (the spatial
+ * averages <u_a^2> of Tests 3-7 are sum_u2[a] / N; mass and momentum are
+ * conserved by the collision and the streaming, eq. cm_collision with
+ * Lambda = 1 and I~ = 0 on modes 0-3).
+ * Statistics rows of the steps completed since the previous call (or since
  * init), oldest first, at most min(cap, series_capacity) of them (the most
  * recent ones); *n_out receives the count.  Synchronises.  Returns
  * CMF_ENONFINITE (after filling `out`) when one of the returned rows counts
@@ -235,10 +260,12 @@ int cmf_get_step(cmf_lattice *lat, int64_t *step);
 int cmf_stats(cmf_lattice *lat, cmf_moments *out, int64_t cap,
               int64_t *n_out);
 
-/* Write the density and velocity of the current pre-collision state as
- * FP32 into device buffers: rho_dev (N floats) and u_dev (3 x N floats,
- * u_x block first).  Either pointer may be NULL.  Asynchronous on the
- * lattice's stream. */
+/* Write the density and velocity of the current pre-collision state
+ * (eq. macro: rho = sum f, rho u = sum c f, evaluated in FP64 and rounded
+ * to FP32) into device buffers on the lattice's device: rho_dev (N floats)
+ * and u_dev (3 x N floats, u_x block first; u_z = 0 on D2Q9); both are
+ * owned by the caller.  Either pointer may be NULL.  Asynchronous on the
+ * lattice's stream.  Errors: CMF_EINVAL (NULL lattice), CMF_EHIP. */
 int cmf_sample_macro(cmf_lattice *lat, void *rho_dev, void *u_dev);
 
 /* The density and velocity of the current pre-collision state, computed on
@@ -267,8 +294,9 @@ int cmf_velocity_pdf(cmf_lattice *lat, int32_t nbins, double xmax, double *momen
  * noisy modes of `n` consecutive sites starting at `site0` of step `step`.
  * out: n x q host doubles, zero on the conserved modes.  `fp64` selects
  * the FP64 transform (as in F64 storage) instead of the FP32 one.  Runs a
- * device kernel on the null stream; synchronous. */
-int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step,
+ * device kernel on the null stream; synchronous.  Errors: CMF_EINVAL (q,
+ * step outside [0, 2^56), sites outside [0, 2^32)), CMF_ENOMEM, CMF_EHIP. */
+int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, int64_t step,
                      int64_t site0, int64_t n, int32_t fp64, double *out);
 
 /* Diagnostic: Philox4x32-10 words for n counters (ctr[4k..4k+3]) under one
@@ -386,6 +414,9 @@ int cmf_ensemble_profile_steps(cmf_ensemble *ens, int64_t nsteps,
 /* Wait for the ensemble's stream; index of the next step. */
 int cmf_ensemble_synchronize(cmf_ensemble *ens);
 int cmf_ensemble_get_step(cmf_ensemble *ens, int64_t *step);
+
+/* Set the shared step counter (as cmf_set_step). */
+int cmf_ensemble_set_step(cmf_ensemble *ens, int64_t step);
 
 /* Statistics rows of replica `index` since the previous call for that
  * replica, as cmf_stats. */

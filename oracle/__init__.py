@@ -47,7 +47,7 @@ def _load():
     lib.orc_norms.argtypes = [c_int, c_int, _dp]
     lib.orc_equilibrium.argtypes = [c_int, c_double, _dp, _dp]
     lib.orc_paper_lambda.argtypes = [c_int, c_double, _dp]
-    lib.orc_normals.argtypes = [c_int, c_u64, c_u32, c_u32, c_u32, _dp]
+    lib.orc_normals.argtypes = [c_int, c_u64, c_u32, c_u64, c_u32, _dp]
     lib.orc_philox4x32_10.argtypes = [_up, _up, _up]
     lib.orc_philox4x32_10.restype = None
     lib.orc_collide_site.argtypes = [c_int, c_int, c_int, c_double, _dp, _dp, _dp,

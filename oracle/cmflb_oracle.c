@@ -39,9 +39,11 @@
  *    f_eq = T(u)^-1 rho e_0 (LU solve) as the equilibrium.  The second
  *    reconstruction path does not apply on D3Q19 (N(u)^-1 != N(-u) there).
  *  - Noise: eta comes from Philox4x32-10 (Salmon et al., SC'11) keyed by the
- *    64-bit seed, counter (site, step, replica, block), mapped to normals by
- *    the Box-Muller transform (details at orc_normals).  The paper asks only
- *    for independent standard normal variables.
+ *    64-bit seed, counter (site, step, replica, block) -- for steps of 2^32
+ *    and beyond (site, step mod 2^32, replica, block + 2^8 floor(step /
+ *    2^32)), so that no two steps below 2^56 share a counter -- mapped to
+ *    normals by the Box-Muller transform (details at normals()).  The paper
+ *    asks only for independent standard normal variables.
  *
  * Parity pins: see the test suite (tests/test_oracle_*.py).  The Philox
  * generator has no published known-answer vector in this repository; it is
@@ -384,20 +386,22 @@ static int first_noisy_mode(int q) { return q == 9 ? 3 : 4; }
 
 /* Standard normals eta_v for the noisy modes v = first..q-1 (Sec. 2.2:
  * I~ = diag[0,0,0,1,..]; Sec. 2.3: I~_0-3 = 0).  Normal n = v - first; pair
- * p = n / 2 draws Philox block p / 2 with counter (site, step, replica,
- * block) and key (seed low word, seed high word), using words
+ * p = n / 2 draws Philox block p / 2 with counter (site, step mod 2^32,
+ * replica, block + 2^8 floor(step / 2^32)) and key (seed low word, seed
+ * high word), using words
  * (2 (p mod 2), 2 (p mod 2) + 1) = (a, b);
  * u1 = ((a >> 8) + 1) 2^-24 in (0, 1], u2 = (b >> 8) 2^-24 in [0, 1),
  * r = sqrt(-2 ln u1), theta = 2 pi u2; even n takes r cos(theta), odd n
  * r sin(theta).  eta[v] = 0 for the conserved modes. */
-static void normals(int q, uint64_t seed, uint32_t replica, uint32_t step,
+static void normals(int q, uint64_t seed, uint32_t replica, uint64_t step,
                     uint32_t site, double *eta) {
   const int first = first_noisy_mode(q);
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   for (int v = 0; v < q; ++v) eta[v] = 0.0;
   for (int v = first; v < q; ++v) {
     int n = v - first, p = n / 2, blk = p / 2, wsel = 2 * (p % 2);
-    uint32_t ctr[4] = {site, step, replica, (uint32_t)blk}, out[4];
+    uint32_t ctr[4] = {site, (uint32_t)step, replica,
+                       (uint32_t)blk + ((uint32_t)(step >> 32) << 8)}, out[4];
     orc_philox4x32_10(ctr, key, out);
     uint32_t a = out[wsel], b = out[wsel + 1];
     double u1 = ((double)(a >> 8) + 1.0) * ldexp(1.0, -24);
@@ -609,7 +613,7 @@ int orc_paper_lambda(int q, double omega, double *lambda) {
   return 0;
 }
 
-int orc_normals(int q, uint64_t seed, uint32_t replica, uint32_t step,
+int orc_normals(int q, uint64_t seed, uint32_t replica, uint64_t step,
                 uint32_t site, double *eta) {
   if (!lattice_ok(q)) return -1;
   normals(q, seed, replica, step, site, eta);
@@ -671,7 +675,7 @@ int orc_run(int q, int basis, int method, int nx, int ny, int nz, double kT,
   (void)nthreads;
 #endif
   for (int64_t t = 0; t < nsteps; ++t) {
-    const uint32_t step = (uint32_t)(step0 + t);
+    const uint64_t step = (uint64_t)(step0 + t);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int64_t row = 0; row < nrows; ++row) {

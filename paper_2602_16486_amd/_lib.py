@@ -73,9 +73,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def library_path():
-    """The in-tree build, or the file named by CMFLB_LIBRARY (an alternative
-    build of the same sources, e.g. a tuning variant)."""
-    return os.environ.get("CMFLB_LIBRARY") or os.path.join(HERE, "libcmflb.so")
+    """The in-tree build (the only library the binding loads)."""
+    return os.path.join(HERE, "libcmflb.so")
 
 
 def load():
@@ -110,6 +109,7 @@ def load():
     lib.cmf_synchronize.argtypes = [vp]
     lib.cmf_profile_steps.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
     lib.cmf_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_set_step.argtypes = [vp, i64]
     lib.cmf_stats.argtypes = [vp, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_sample_macro.argtypes = [vp, vp, vp]
     lib.cmf_get_macro.argtypes = [vp, _dp, _dp]
@@ -118,7 +118,7 @@ def load():
     lib.cmf_external_bytes.argtypes = [ctypes.POINTER(Desc)]
     lib.cmf_external_bytes.restype = ctypes.c_size_t
     lib.cmf_velocity_pdf.argtypes = [vp, i32, ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64)]
-    lib.cmf_noise_sample.argtypes = [i32, u64, u32, u32, i64, i64, i32, _dp]
+    lib.cmf_noise_sample.argtypes = [i32, u64, u32, i64, i64, i64, i32, _dp]
     lib.cmf_philox_words.argtypes = [ctypes.POINTER(ctypes.c_uint32), i64, u32, u32,
                                      ctypes.POINTER(ctypes.c_uint32)]
     lib.cmf_stream_copy.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double)]
@@ -136,6 +136,7 @@ def load():
     lib.cmf_ensemble_profile_steps.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
     lib.cmf_ensemble_synchronize.argtypes = [vp]
     lib.cmf_ensemble_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.cmf_ensemble_set_step.argtypes = [vp, i64]
     lib.cmf_ensemble_stats.argtypes = [vp, i32, ctypes.POINTER(Moments), i64, ctypes.POINTER(ctypes.c_int64)]
     lib.cmf_ensemble_get_tiles.argtypes = [vp, ctypes.POINTER(EnsembleTiles)]
     lib.cmf_ensemble_set_tiles.argtypes = [vp, i32, i32]
@@ -149,12 +150,13 @@ def load():
     for name in ("cmf_ensemble_create", "cmf_ensemble_destroy", "cmf_ensemble_info",
                  "cmf_ensemble_init_equilibrium", "cmf_ensemble_set_populations",
                  "cmf_ensemble_get_populations", "cmf_ensemble_step", "cmf_ensemble_profile_steps",
-                 "cmf_ensemble_synchronize", "cmf_ensemble_get_step", "cmf_ensemble_stats",
+                 "cmf_ensemble_synchronize", "cmf_ensemble_get_step", "cmf_ensemble_set_step",
+                 "cmf_ensemble_stats",
                  "cmf_ensemble_get_tiles", "cmf_ensemble_set_tiles", "cmf_ensemble_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cmf_get_launch", "cmf_set_launch", "cmf_autotune", "cmf_stream_copy", "cmf_create", "cmf_destroy", "cmf_init_equilibrium", "cmf_set_populations",
                  "cmf_get_populations", "cmf_gather_sites", "cmf_step", "cmf_synchronize",
-                 "cmf_get_step", "cmf_stats", "cmf_sample_macro", "cmf_get_macro", "cmf_velocity_pdf",
+                 "cmf_get_step", "cmf_set_step", "cmf_stats", "cmf_sample_macro", "cmf_get_macro", "cmf_velocity_pdf",
                  "cmf_noise_sample",
                  "cmf_philox_words", "cmf_device_count", "cmf_profile_steps"):
         getattr(lib, name).restype = ctypes.c_int

@@ -46,6 +46,8 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr double kCs2 = 1.0 / 3.0;
 constexpr int kGraphSteps = 32;
+// noise counters are distinct for steps below 2^56 (see site_normals)
+constexpr int64_t kMaxStep = (int64_t)1 << 56;
 
 // one-axis weights of the rest state: w(0) = 2/3, w(+-1) = 1/6; the D2Q9 and
 // D3Q27 weights of Sec. 2.2 / 2.3 are their products (4/9, 1/9, 1/36 and
@@ -164,7 +166,6 @@ void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
   mc.general = false;
   for (int v = first_noisy(q); v < q; ++v)
     if (!is_omega_mode(q, v) && mc.lambda[v] != 1.0) mc.general = true;
-  if (env_int("CMF_FORCE_GENERAL", 0)) mc.general = true;
   double b[27];
   if (q == 9)
     lattice_weights<D2Q9>(mc.w);
@@ -226,18 +227,18 @@ int forked_init(ForkedRun &F) {
   return CMF_OK;
 }
 
-// step(j, stream) enqueues step j; fin(j, stream) its statistics reduction
-// (only when `stats`).
+// Enqueue a run of n <= kGraphSteps steps in the forked form on stream s:
+// step(j, stream) enqueues step j (step offset j, partial-sum buffer j mod
+// 2); fin(j, stream) its statistics reduction (only when `stats`), on the
+// second stream; the step counter advances by n at the end.  Used inside a
+// graph capture (runs of kGraphSteps) and directly (the remainder of a
+// cmf_step call), so the statistics of direct steps overlap the next step
+// as well.
 template <class StepFn, class FinFn>
-int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step,
-                   FinFn fin, hipGraphExec_t *out) {
-  if (stats) {
-    int rc = forked_init(F);
-    if (rc != CMF_OK) return rc;
-  }
-  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+hipError_t enqueue_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev,
+                          StepFn step, FinFn fin, int n) {
   hipError_t e = hipSuccess;
-  for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j) {
+  for (int j = 0; j < n && e == hipSuccess; ++j) {
     if (stats && j >= 2) e = hipStreamWaitEvent(s, F.ev_fin[j - 2], 0);
     if (e == hipSuccess) e = step(j, s);
     if (stats) {
@@ -247,8 +248,33 @@ int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, S
       if (e == hipSuccess) e = hipEventRecord(F.ev_fin[j], F.aux);
     }
   }
-  if (stats && e == hipSuccess) e = hipStreamWaitEvent(s, F.ev_fin[kGraphSteps - 1], 0);
-  if (e == hipSuccess) e = launch_bump_step(step_dev, kGraphSteps, s);
+  if (stats && e == hipSuccess) e = hipStreamWaitEvent(s, F.ev_fin[n - 1], 0);
+  if (e == hipSuccess) e = launch_bump_step(step_dev, n, s);
+  return e;
+}
+
+template <class StepFn, class FinFn>
+int run_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step, FinFn fin,
+               int n) {
+  if (n < 1 || n > kGraphSteps) return fail(CMF_EINVAL, "internal: forked run of %d steps", n);
+  if (stats) {
+    int rc = forked_init(F);
+    if (rc != CMF_OK) return rc;
+  }
+  const hipError_t e = enqueue_forked(s, F, stats, step_dev, step, fin, n);
+  if (e != hipSuccess) return fail(CMF_EHIP, "step launch failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
+
+template <class StepFn, class FinFn>
+int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step,
+                   FinFn fin, hipGraphExec_t *out) {
+  if (stats) {
+    int rc = forked_init(F);
+    if (rc != CMF_OK) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_forked(s, F, stats, step_dev, step, fin, kGraphSteps);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(s, &g);
   if (e == hipSuccess) e = ec;
@@ -367,6 +393,12 @@ std::string tune_key(const cmf_lattice *L) {
   return b;
 }
 
+// launch shapes the step kernels support: block threads per workgroup a
+// multiple of 64 up to 256 (the statistics reduction assumes it), grid >= 1
+bool valid_launch(int block, int grid) {
+  return (block == 64 || block == 128 || block == 192 || block == 256) && grid >= 1;
+}
+
 void load_tune_file_locked() {
   if (g_tune_file_loaded) return;
   g_tune_file_loaded = true;
@@ -377,7 +409,9 @@ void load_tune_file_locked() {
   char key[160];
   int block, grid;
   double ms;
-  while (fscanf(f, "%159s %d %d %lf", key, &block, &grid, &ms) == 4) g_tuned[key] = {block, grid};
+  // only shapes that cmf_set_launch would accept; other lines are skipped
+  while (fscanf(f, "%159s %d %d %lf", key, &block, &grid, &ms) == 4)
+    if (valid_launch(block, grid)) g_tuned[key] = {block, grid};
   fclose(f);
 }
 
@@ -493,18 +527,38 @@ int time_full_steps(cmf_lattice *L, int n, double *ms_out) {
   return CMF_OK;
 }
 
-int capture_graph(cmf_lattice *L, int parity) {
-  const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
-  auto step = [&](int j, hipStream_t s) {
+// Steps of a forked run starting from buffer `parity` (step j reads
+// buf[parity ^ (j & 1)]) and their statistics reductions.
+struct LatticeRun {
+  cmf_lattice *L;
+  int parity;
+  hipError_t operator()(int j, hipStream_t s) const {
     const int b = parity ^ (j & 1);
     return launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), L->buf[b],
                        L->buf[b ^ 1], L->step_dev, j, partials_buf(L, j & 1), L->grid, L->block, s);
-  };
-  auto fin = [&](int j, hipStream_t s) {
+  }
+};
+struct LatticeFin {
+  cmf_lattice *L;
+  hipError_t operator()(int j, hipStream_t s) const {
     return launch_finalize(partials_buf(L, j & 1), L->nparts, L->level2, L->series, L->cap,
                            L->step_dev, j, 0, L->mass0, true, s);
-  };
-  return capture_forked(L->stream, L->forked, stats, L->step_dev, step, fin, &L->graph[parity]);
+  }
+};
+
+int capture_graph(cmf_lattice *L, int parity) {
+  const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
+  return capture_forked(L->stream, L->forked, stats, L->step_dev, LatticeRun{L, parity},
+                        LatticeFin{L}, &L->graph[parity]);
+}
+
+// n <= kGraphSteps direct steps in the forked form
+int run_direct(cmf_lattice *L, int n) {
+  const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
+  int rc = run_forked(L->stream, L->forked, stats, L->step_dev, LatticeRun{L, L->parity},
+                      LatticeFin{L}, n);
+  if (rc == CMF_OK) L->parity ^= (n & 1);
+  return rc;
 }
 
 void release(cmf_lattice *L) {
@@ -854,9 +908,11 @@ int cmf_step(cmf_lattice *L, int64_t nsteps) {
     HIP_TRY(hipGraphLaunch(L->graph[L->parity], L->stream));
     left -= kGraphSteps;  // an even number of steps: parity unchanged
   }
-  for (; left > 0; --left) {
-    int rc = enqueue_one_step(L);
+  while (left > 0) {
+    const int n = left < kGraphSteps ? (int)left : kGraphSteps;
+    int rc = run_direct(L, n);
     if (rc != CMF_OK) return rc;
+    left -= n;
   }
   return CMF_OK;
 }
@@ -1108,6 +1164,16 @@ int cmf_get_step(cmf_lattice *L, int64_t *step) {
   return CMF_OK;
 }
 
+int cmf_set_step(cmf_lattice *L, int64_t step) {
+  if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  if (step < 0 || step >= kMaxStep)
+    return fail(CMF_EINVAL, "step %lld outside [0, 2^56)", (long long)step);
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  HIP_TRY(hipMemcpy(L->step_dev, &step, sizeof(int64_t), hipMemcpyHostToDevice));
+  L->read_step = step;
+  return CMF_OK;
+}
+
 int cmf_stats(cmf_lattice *L, cmf_moments *out, int64_t cap, int64_t *n_out) {
   if (!L || !n_out || (cap > 0 && !out)) return fail(CMF_EINVAL, "NULL argument");
   if (cap < 0) return fail(CMF_EINVAL, "cap < 0");
@@ -1247,15 +1313,17 @@ int cmf_velocity_pdf(cmf_lattice *L, int32_t nbins, double xmax, double *moments
   return CMF_OK;
 }
 
-int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, uint32_t step, int64_t site0,
+int cmf_noise_sample(int32_t q, uint64_t seed, uint32_t replica, int64_t step, int64_t site0,
                      int64_t n, int32_t fp64, double *out) {
   if (q != 9 && q != 19 && q != 27) return fail(CMF_EINVAL, "q must be 9, 19 or 27");
+  if (step < 0 || step >= kMaxStep) return fail(CMF_EINVAL, "step outside [0, 2^56)");
   if (n < 0 || site0 < 0 || site0 + n > ((int64_t)1 << 32)) return fail(CMF_EINVAL, "bad site range");
   if (n == 0) return CMF_OK;
   if (!out) return fail(CMF_EINVAL, "out is NULL");
   double *d = nullptr;
   if (hipMalloc((void **)&d, sizeof(double) * q * n) != hipSuccess) return fail(CMF_ENOMEM, "hipMalloc failed");
-  hipError_t e = launch_noise(q, fp64, (uint32_t)seed, (uint32_t)(seed >> 32), replica, step, site0, n, d,
+  hipError_t e = launch_noise(q, fp64, (uint32_t)seed, (uint32_t)(seed >> 32), replica, (uint64_t)step,
+                              site0, n, d,
                               nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(out, d, sizeof(double) * q * n, hipMemcpyDeviceToHost);
@@ -1433,19 +1501,36 @@ int ens_enqueue_step(cmf_ensemble *E) {
   return CMF_OK;
 }
 
-int ens_capture(cmf_ensemble *E, int parity) {
-  const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
-  auto step = [&](int j, hipStream_t s) {
+struct EnsembleRun {
+  cmf_ensemble *E;
+  int parity;
+  hipError_t operator()(int j, hipStream_t s) const {
     const int b = parity ^ (j & 1);
     return launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep,
                                 E->ntiles, E->arena[b], E->arena[b ^ 1], E->step_dev, j,
                                 ens_partials_buf(E, j & 1), s);
-  };
-  auto fin = [&](int j, hipStream_t s) {
+  }
+};
+struct EnsembleFin {
+  cmf_ensemble *E;
+  hipError_t operator()(int j, hipStream_t s) const {
     return launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, j & 1),
                                     E->series, E->cap, E->step_dev, j, 0, E->d_mass0, true, s);
-  };
-  return capture_forked(E->stream, E->forked, stats, E->step_dev, step, fin, &E->graph[parity]);
+  }
+};
+
+int ens_capture(cmf_ensemble *E, int parity) {
+  const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
+  return capture_forked(E->stream, E->forked, stats, E->step_dev, EnsembleRun{E, parity},
+                        EnsembleFin{E}, &E->graph[parity]);
+}
+
+int ens_run_direct(cmf_ensemble *E, int n) {
+  const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
+  int rc = run_forked(E->stream, E->forked, stats, E->step_dev, EnsembleRun{E, E->parity},
+                      EnsembleFin{E}, n);
+  if (rc == CMF_OK) E->parity ^= (n & 1);
+  return rc;
 }
 
 int ens_check_index(cmf_ensemble *E, int32_t index) {
@@ -1799,9 +1884,11 @@ int cmf_ensemble_step(cmf_ensemble *E, int64_t nsteps) {
     HIP_TRY(hipGraphLaunch(E->graph[E->parity], E->stream));
     left -= kGraphSteps;
   }
-  for (; left > 0; --left) {
-    int rc = ens_enqueue_step(E);
+  while (left > 0) {
+    const int n = left < kGraphSteps ? (int)left : kGraphSteps;
+    int rc = ens_run_direct(E, n);
     if (rc != CMF_OK) return rc;
+    left -= n;
   }
   return CMF_OK;
 }
@@ -1850,6 +1937,16 @@ int cmf_ensemble_get_step(cmf_ensemble *E, int64_t *step) {
   if (!E || !step) return fail(CMF_EINVAL, "NULL argument");
   HIP_TRY(hipStreamSynchronize(E->stream));
   HIP_TRY(hipMemcpy(step, E->step_dev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return CMF_OK;
+}
+
+int cmf_ensemble_set_step(cmf_ensemble *E, int64_t step) {
+  if (!E) return fail(CMF_EINVAL, "ensemble is NULL");
+  if (step < 0 || step >= kMaxStep)
+    return fail(CMF_EINVAL, "step %lld outside [0, 2^56)", (long long)step);
+  HIP_TRY(hipStreamSynchronize(E->stream));
+  HIP_TRY(hipMemcpy(E->step_dev, &step, sizeof(int64_t), hipMemcpyHostToDevice));
+  for (auto &r : E->read_step) r = step;
   return CMF_OK;
 }
 

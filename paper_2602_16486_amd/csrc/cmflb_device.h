@@ -218,13 +218,20 @@ __device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b,
 }
 
 // The NNOISE normals of one site and step, eta[n] for mode FIRST_NOISY + n.
+// Counter (site, step mod 2^32, replica, block + 2^8 floor(step / 2^32)):
+// the block index takes 8 bits, so the counters of all steps below 2^56
+// are distinct, and steps below 2^32 keep the plain (site, step, replica,
+// block) counter.  The step is wave-uniform, so its two words cost scalar
+// operations only.
 template <class L, typename R>
-__device__ __forceinline__ void site_normals(uint32_t site, uint32_t step,
+__device__ __forceinline__ void site_normals(uint32_t site, uint64_t step,
                                              uint32_t replica, uint32_t k0,
                                              uint32_t k1, R *eta) {
+  const uint32_t step_lo = (uint32_t)step;
+  const uint32_t blk_hi = (uint32_t)(step >> 32) << 8;
 #pragma unroll
   for (int blk = 0; blk < L::NBLOCKS; ++blk) {
-    const U4 w = philox4x32_10(site, step, replica, (uint32_t)blk, k0, k1);
+    const U4 w = philox4x32_10(site, step_lo, replica, (uint32_t)blk | blk_hi, k0, k1);
     const int n0 = 4 * blk;
     R a, b;
     box_muller<R>(w.x, w.y, a, b);

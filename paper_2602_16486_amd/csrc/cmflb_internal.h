@@ -98,7 +98,7 @@ hipError_t launch_macro(int q, int storage, const ConvParams &cp,
                         const void *buf, double *rho, double *u,
                         hipStream_t stream);
 hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
-                        uint32_t replica, uint32_t step, int64_t site0,
+                        uint32_t replica, uint64_t step, int64_t site0,
                         int64_t n, double *out, hipStream_t stream);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
                          uint32_t key1, uint32_t *out, hipStream_t stream);

@@ -102,7 +102,7 @@ __device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
 // slightly faster with the per-mode values.
 template <class L, typename R, bool GENERAL, bool LEAN, class P, class A>
 __device__ __forceinline__ void collide_tensor(R *d, const P &p,
-                                               uint32_t site, uint32_t step,
+                                               uint32_t site, uint64_t step,
                                                A &acc) {
   constexpr int Q = L::Q;
   // step 1: rho = rho0 + sum d, rho u = sum c d (eq. macro).  D3Q27 forms
@@ -294,7 +294,7 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
 // (M_7 = c_x c_y, M_8 = c_y c_z, M_9 = c_x c_z); k_eq = (rho, 0, ..., 0).
 template <typename R, bool GENERAL, bool LEAN, class P, class A>
 __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
-                                              uint32_t step, A &acc) {
+                                              uint64_t step, A &acc) {
   using L = D3Q19;
   R r[19];
   d3q19::raw_moments(d, r);
@@ -364,7 +364,7 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
 
 template <class L, typename R, bool GENERAL, bool LEAN, class P, class A>
 __device__ __forceinline__ void collide_site(R *d, const P &p, uint32_t site,
-                                             uint32_t step, A &acc) {
+                                             uint64_t step, A &acc) {
   if constexpr (L::Q == 19)
     collide_d3q19<R, GENERAL, LEAN>(d, p, site, step, acc);
   else
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
     const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
     const int64_t *__restrict__ step_ptr, int step_off, double *__restrict__ partials) {
   constexpr int Q = L::Q;
-  const uint32_t step = (uint32_t)(*step_ptr + step_off);
+  const uint64_t step = (uint64_t)(*step_ptr + step_off);
   const int BX = blockDim.x;
   const int nx = p.nx, ny = p.ny;
   using A = typename std::conditional<ONE, SiteStats<R>, Acc>::type;
@@ -789,7 +789,7 @@ __global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
 
 template <class L, typename R>
 __global__ __launch_bounds__(256) void k_noise(uint32_t key0, uint32_t key1,
-                                               uint32_t replica, uint32_t step,
+                                               uint32_t replica, uint64_t step,
                                                int64_t site0, int64_t n,
                                                double *__restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1082,7 +1082,7 @@ template <class L, typename S, typename R, bool GENERAL, bool NT>
 __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
                                               S *__restrict__ dst,
                                               const ReplicaParams<R> &p,
-                                              int64_t s, uint32_t step,
+                                              int64_t s, uint64_t step,
                                               Acc &acc) {
   const uint32_t nx = (uint32_t)p.nx, ny = (uint32_t)p.ny;
   const uint32_t us = (uint32_t)s;
@@ -1119,7 +1119,7 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
     const int64_t *__restrict__ step_ptr, int step_off, double *__restrict__ partials) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const ReplicaParams<R> &p = reps[tile_rep[tile]];
-  const uint32_t step = (uint32_t)(*step_ptr + step_off);
+  const uint64_t step = (uint64_t)(*step_ptr + step_off);
   Acc acc;
 #pragma unroll
   for (int k = 0; k < kNAcc; ++k) acc.v[k] = 0.0;
@@ -1371,7 +1371,7 @@ hipError_t launch_macro(int q, int storage, const ConvParams &cp,
 }
 
 hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
-                        uint32_t replica, uint32_t step, int64_t site0,
+                        uint32_t replica, uint64_t step, int64_t site0,
                         int64_t n, double *out, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const unsigned g = blocks_for(n, 256);

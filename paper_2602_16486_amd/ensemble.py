@@ -119,6 +119,12 @@ class Ensemble:
         _lib.check(self._lib.cmf_ensemble_get_step(self._h, ctypes.byref(v)))
         return v.value
 
+    @step_index.setter
+    def step_index(self, step):
+        """Set the index of the next step (resuming a saved run continues its
+        noise sequence)."""
+        _lib.check(self._lib.cmf_ensemble_set_step(self._h, int(step)))
+
     def stats(self, index, cap=1 << 16, raise_nonfinite=True):
         """Statistics rows of replica ``index`` since the previous call, as
         :meth:`Lattice.stats`."""

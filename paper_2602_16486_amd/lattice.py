@@ -217,6 +217,12 @@ class Lattice:
         _lib.check(self._lib.cmf_get_step(self._h, ctypes.byref(v)))
         return v.value
 
+    @step_index.setter
+    def step_index(self, step):
+        """Set the index of the next step (resuming a saved run continues its
+        noise sequence)."""
+        _lib.check(self._lib.cmf_set_step(self._h, int(step)))
+
     def stats(self, cap=1 << 20, raise_nonfinite=True):
         """(n, 12) array of the per-step statistics rows recorded since the
         previous call (columns ``_lib.STAT_COLUMNS``), at most the last

@@ -52,27 +52,37 @@ def test_d2q9_64_full_run(storage, d2q9_64_oracle):
     assert c["momentum_drift"] < (1e-10 if storage == "f64" else 1e-4)
 
 
-@pytest.fixture(scope="module")
-def d3q27_64_oracle():
-    q, shape, kT, tau, steps, every = 27, (64, 64, 64), 1e-4, 0.8, 120, 20
-    n = 64 ** 3
-    f = O.init_equilibrium(q, n, 1.0)
-    lam = O.paper_lambda(q, 1 / tau)
-    sa = spectra.ShellAverager(shape, 16)
-    rows = []
-    for k in range(steps // every):
-        rows.append(O.run(q, shape, f, kT, lam, 1, 0, k * every, every))
-        sa.add(spectra.fields(q, shape, f, 1.0))
-    return np.concatenate(rows), sa.shells()
+_d3q27_64_cache = {}
 
 
+def d3q27_64_oracle(tau, kT):
+    """The oracle's 64^3 run (120 steps, S(k) every 20) for one (tau, kT)."""
+    key = (tau, kT)
+    if key not in _d3q27_64_cache:
+        q, shape, steps, every = 27, (64, 64, 64), 120, 20
+        n = 64 ** 3
+        f = O.init_equilibrium(q, n, 1.0)
+        lam = O.paper_lambda(q, 1 / tau)
+        sa = spectra.ShellAverager(shape, 16)
+        rows = []
+        for k in range(steps // every):
+            rows.append(O.run(q, shape, f, kT, lam, 1, 0, k * every, every))
+            sa.add(spectra.fields(q, shape, f, 1.0))
+        _d3q27_64_cache[key] = (np.concatenate(rows), sa.shells())
+    return _d3q27_64_cache[key]
+
+
+@pytest.mark.parametrize("tau,kT", [(0.8, 1e-4), (0.8, 1e-5), (0.51, 1e-4), (0.51, 1e-5)])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_d3q27_64_storage_against_oracle(storage, d3q27_64_oracle):
-    """64^3 subrun of the 256^3 storage comparison: <u^2> (averaged over the
-    run) within 1% of the FP64 oracle for every storage type, and the
-    structure factor shells within 2% (FP32 within 1e-4)."""
-    q, shape, kT, tau, steps, every = 27, (64, 64, 64), 1e-4, 0.8, 120, 20
-    st_ref, sk_ref = d3q27_64_oracle
+def test_d3q27_64_storage_against_oracle(storage, tau, kT):
+    """64^3 subrun of the 256^3 storage comparison at the storage workload's
+    relaxation times and thermal energies (tau = 0.51 over-relaxes the modes
+    relaxed at omega, 1 - omega = -0.96, so their storage rounding decays
+    slowest): <u^2> (averaged over the run) within 1% of the FP64 oracle for
+    every storage type, and the structure factor shells within 2% (FP32
+    within 1e-4)."""
+    q, shape, steps, every = 27, (64, 64, 64), 120, 20
+    st_ref, sk_ref = d3q27_64_oracle(tau, kT)
     with Lattice(q, shape, storage=storage, tau=tau, kT=kT, seed=1) as lat:
         lat.sk_reset(16)
         for _ in range(steps // every):
@@ -86,9 +96,9 @@ def test_d3q27_64_storage_against_oracle(storage, d3q27_64_oracle):
     rel = abs(u2[20:].mean() / u2_ref[20:].mean() - 1)
     # step 0 is the rest state (u = 0 on both sides)
     per_step = np.abs(u2[1:] / u2_ref[1:] - 1).max()
-    print(f"D3Q27 64^3 {storage}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
+    print(f"D3Q27 64^3 {storage} tau={tau} kT={kT}: <u^2> rel diff {rel:.2e}, worst step {per_step:.2e}")
     assert rel < (1e-4 if storage == "f32" else 1e-2)
     sel = sk_ref[:, 1] > 0
     srel = np.abs(sk[sel, 2:5] / sk_ref[sel, 2:5] - 1).max()
-    print(f"D3Q27 64^3 {storage}: S(k) worst shell rel diff {srel:.2e}")
+    print(f"D3Q27 64^3 {storage} tau={tau} kT={kT}: S(k) worst shell rel diff {srel:.2e}")
     assert srel < (1e-4 if storage == "f32" else 2e-2)

@@ -122,3 +122,50 @@ def test_normals_finite_at_extreme_words():
     assert np.sqrt(-2 * np.log(2.0 ** -24)) < 6.0
     eta = np.array([O.normals(9, s, 0, 0, 0) for s in range(2000)])
     assert np.all(np.isfinite(eta)) and np.abs(eta).max() < 6.0
+
+
+def _normals_from_definition(q, seed, replica, step, site):
+    """eta of the stated mapping, evaluated here from Philox words: normal
+    n = v - first of pair p = n // 2 takes block p // 2, words 2 (p % 2) and
+    2 (p % 2) + 1 as (a, b); u1 = ((a >> 8) + 1) 2^-24, u2 = (b >> 8) 2^-24,
+    r = sqrt(-2 ln u1), cosine for even n; counter (site, step mod 2^32,
+    replica, block + 2^8 floor(step / 2^32))."""
+    first = 3 if q == 9 else 4
+    key = [seed & MASK, seed >> 32]
+    eta = np.zeros(q)
+    for v in range(first, q):
+        n = v - first
+        p = n // 2
+        blk = p // 2
+        ctr = [site, step & MASK, replica, blk + ((step >> 32) << 8)]
+        w = O.philox4x32_10(ctr, key)
+        a, b = int(w[2 * (p % 2)]), int(w[2 * (p % 2) + 1])
+        u1 = ((a >> 8) + 1) * 2.0 ** -24
+        u2 = (b >> 8) * 2.0 ** -24
+        r = np.sqrt(-2.0 * np.log(u1))
+        eta[v] = r * (np.cos(2 * np.pi * u2) if n % 2 == 0 else np.sin(2 * np.pi * u2))
+    return eta
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+@pytest.mark.parametrize("step", [0, 5, (1 << 32) - 1, 1 << 32, (1 << 32) + 7, (1 << 40) + 3, (1 << 56) - 1])
+def test_normals_follow_the_stated_mapping(q, step):
+    """The counter layout, word selection and Box-Muller transform stated for
+    the noise, including the steps of 2^32 and beyond (whose counters carry
+    the high step bits next to the block index)."""
+    seed, replica = (1 << 33) + 77, 5
+    for site in (0, 1, 4095, (1 << 32) - 1):
+        got = O.normals(q, seed, replica, step, site)
+        ref = _normals_from_definition(q, seed, replica, step, site)
+        assert np.abs(got - ref).max() < 1e-14
+
+
+def test_normals_of_steps_2_to_the_32_apart_differ():
+    """The paper's normals are independent at every step: steps t and
+    t + 2^32 (and t + 2^40) draw different normals, where a 32-bit step
+    word would repeat them."""
+    for t in (0, 3, 1000):
+        base = O.normals(27, 9, 1, t, 17)
+        for far in (t + (1 << 32), t + (1 << 40)):
+            other = O.normals(27, 9, 1, far, 17)
+            assert np.abs(other[4:] - base[4:]).min() > 0.0
