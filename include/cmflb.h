@@ -235,6 +235,30 @@ int cmf_set_launch(cmf_lattice *lat, int32_t block, int32_t grid);
 int cmf_autotune(cmf_lattice *lat, int32_t steps_per_trial, cmf_launch *trials,
                  int32_t cap, int32_t *n_out);
 
+/* One time step without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The step is the one cmf_step takes (same kernels,
+ * same results), for the lattice `desc` describes, from the state in `src`
+ * to `dst`: two different device buffers of the current device, each
+ * 256-byte aligned and holding q x N elements of the storage type in the
+ * library's internal layout -- the two halves of a cmf_create_external
+ * buffer (deviations f - w rho0, scaled for 16-bit storage, row-interleaved;
+ * write and read them through such a lattice).  `step` (in [0, 2^56)) is
+ * the index whose noise the step draws; the launch shape is (`block`,
+ * `grid`) as in cmf_set_launch, with grid at most 65536 (larger grids are
+ * rejected: the scratch holds the partial sums of that many workgroups).
+ * When `stats_dev` is not NULL it receives the statistics row of the step
+ * (12 device doubles, laid out as cmf_moments).  The statistics scratch
+ * (partial sums, reduction rows, step counter; about 6.3 MB) is a static
+ * device array, one per GPU, held until the process ends; every call on a
+ * GPU shares it, so calls that overlap on one GPU (different streams or
+ * threads) race and must be serialised by the caller.  Asynchronous on
+ * `hip_stream` (NULL: the null stream); launches kernels only (no memset,
+ * no allocation).  Errors: CMF_EINVAL (desc, buffers, step, launch shape),
+ * CMF_EUNSUPPORTED (device index >= 64), CMF_EHIP. */
+int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst, int64_t step,
+                     int32_t block, int32_t grid, double *stats_dev, void *hip_stream);
+
 /* Wait for all work enqueued on the lattice's stream. */
 int cmf_synchronize(cmf_lattice *lat);
 

@@ -122,6 +122,8 @@ def load():
     lib.cmf_philox_words.argtypes = [ctypes.POINTER(ctypes.c_uint32), i64, u32, u32,
                                      ctypes.POINTER(ctypes.c_uint32)]
     lib.cmf_stream_copy.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.cmf_step_noalloc.argtypes = [ctypes.POINTER(Desc), vp, vp, i64, i32, i32, vp, vp]
+    lib.cmf_step_noalloc.restype = ctypes.c_int
     lib.cmf_get_launch.argtypes = [vp, ctypes.POINTER(Launch)]
     lib.cmf_set_launch.argtypes = [vp, i32, i32]
     lib.cmf_autotune.argtypes = [vp, i32, ctypes.POINTER(Launch), i32, ctypes.POINTER(ctypes.c_int32)]

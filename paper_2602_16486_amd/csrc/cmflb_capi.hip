@@ -358,27 +358,35 @@ void class_scales(int q, int storage, const float *scale, float *cs, float *ics)
   }
 }
 
+// Step-kernel parameters of a lattice description with workgroups of
+// `block` threads.
+template <typename R>
+void fill_params(const cmf_desc &d, const double *lambda, const double *amp, const float *scale,
+                 int block, StepParams<R> &p) {
+  memset(&p, 0, sizeof p);
+  p.nx = d.nx;
+  p.ny = d.ny;
+  p.nz = d.nz;
+  p.nxb = (d.nx + block - 1) / block;
+  p.ntiles = p.nxb * p.ny * p.nz;
+  p.noise = d.kT > 0.0 ? 1 : 0;
+  p.rho0 = (R)d.rho0;
+  for (int v = 0; v < d.q; ++v) {
+    p.amp[v] = (R)amp[v];
+    p.oml[v] = (R)(1.0 - lambda[v]);
+    p.lam[v] = (R)lambda[v];
+  }
+  p.amp1 = (R)sqrt(d.kT / kCs2);
+  class_scales(d.q, d.storage, scale, p.scale, p.iscale);
+  p.key0 = (uint32_t)d.seed;
+  p.key1 = (uint32_t)(d.seed >> 32);
+  p.replica = d.replica;
+}
+
 template <typename R>
 void fill_step_params(const cmf_lattice *L, const double *amp,
                       const float *scale, StepParams<R> &p) {
-  memset(&p, 0, sizeof p);
-  p.nx = L->desc.nx;
-  p.ny = L->desc.ny;
-  p.nz = L->desc.nz;
-  p.nxb = (L->desc.nx + L->block - 1) / L->block;
-  p.ntiles = p.nxb * p.ny * p.nz;
-  p.noise = L->desc.kT > 0.0 ? 1 : 0;
-  p.rho0 = (R)L->desc.rho0;
-  for (int v = 0; v < L->q; ++v) {
-    p.amp[v] = (R)amp[v];
-    p.oml[v] = (R)(1.0 - L->lambda[v]);
-    p.lam[v] = (R)L->lambda[v];
-  }
-  p.amp1 = (R)sqrt(L->desc.kT / kCs2);
-  class_scales(L->q, L->storage, scale, p.scale, p.iscale);
-  p.key0 = (uint32_t)L->desc.seed;
-  p.key1 = (uint32_t)(L->desc.seed >> 32);
-  p.replica = L->desc.replica;
+  fill_params(L->desc, L->lambda, amp, scale, L->block, p);
 }
 
 // tuned launch shapes of this process, keyed by device/lattice/storage/box
@@ -1384,6 +1392,91 @@ int cmf_stream_copy(size_t bytes, int32_t reps, double *best_ms) {
 }
 
 }  // extern "C"
+
+// ---- one step without allocation ------------------------------------------
+// Device scratch of cmf_step_noalloc, one copy per GPU the library runs on
+// (held until the process ends): the per-workgroup partial sums of the
+// statistics (kNoAllocMaxGrid rows), the second-level rows of their
+// reduction (kMaxLevel2 rows) and the step counter the kernels read.  In
+// host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (scratch_address).
+namespace {
+constexpr int kNoAllocMaxGrid = 65536;
+constexpr size_t kScratchPartials = (size_t)kNoAllocMaxGrid * kPartStride;
+constexpr size_t kScratchLevel2 = (size_t)kMaxLevel2 * kPartStride;
+constexpr size_t kScratchDoubles = kScratchPartials + kScratchLevel2 + 1;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+int scratch_address(double **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CMF_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(CMF_EUNSUPPORTED, "device %d: at most %d devices are supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CMF_EHIP, "hipGetSymbolAddress of the scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return CMF_OK;
+}
+}  // namespace
+
+extern "C" int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst, int64_t step,
+                                int32_t block, int32_t grid, double *stats_dev,
+                                void *hip_stream) {
+  int rc = validate(desc);
+  if (rc != CMF_OK) return rc;
+  if (!src || !dst || src == dst) return fail(CMF_EINVAL, "src and dst must be two different buffers");
+  if (reinterpret_cast<uintptr_t>(src) % 256 != 0 || reinterpret_cast<uintptr_t>(dst) % 256 != 0)
+    return fail(CMF_EINVAL, "src and dst must be 256-byte aligned");
+  if (step < 0 || step >= kMaxStep)
+    return fail(CMF_EINVAL, "step %lld outside [0, 2^56)", (long long)step);
+  if (!valid_launch(block, grid))
+    return fail(CMF_EINVAL, "block must be 64, 128, 192 or 256 and grid >= 1, got (%d, %d)", block,
+                grid);
+  if (grid > kNoAllocMaxGrid)
+    return fail(CMF_EINVAL,
+                "grid %d exceeds %d: the scratch holds the partial sums of at most %d workgroups",
+                grid, kNoAllocMaxGrid, kNoAllocMaxGrid);
+  double *scr = nullptr;
+  rc = scratch_address(&scr);
+  if (rc != CMF_OK) return rc;
+  ModeConstants mc;
+  mode_constants(desc, mc);
+  StepParams<double> pd;
+  StepParams<float> pf;
+  const bool f64 = desc->storage == kF64;
+  if (f64)
+    fill_params(*desc, mc.lambda, mc.amp, mc.scale, block, pd);
+  else
+    fill_params(*desc, mc.lambda, mc.amp, mc.scale, block, pf);
+  const int ntiles = f64 ? pd.ntiles : pf.ntiles;
+  const int g = grid < ntiles ? grid : ntiles;
+  const bool nt = ((int64_t)desc->nx * storage_bytes(desc->storage)) % kLineBytes == 0;
+  const double mass0 = (double)desc->nx * desc->ny * desc->nz * desc->rho0;
+  int64_t *step_dev = reinterpret_cast<int64_t *>(scr + kScratchPartials + kScratchLevel2);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = launch_set_i64(step_dev, step, s);
+  if (e == hipSuccess)
+    e = launch_step(desc->q, desc->storage, mc.general, nt, f64 ? (const void *)&pd : (const void *)&pf,
+                    src, dst, step_dev, 0, scr, g, block, s);
+  if (e == hipSuccess && stats_dev)
+    e = launch_finalize(scr, g, scr + kScratchPartials, stats_dev, 1, step_dev, 0, 0, mass0, true, s);
+  if (e != hipSuccess) return fail(CMF_EHIP, "step launch failed: %s", hipGetErrorString(e));
+  return CMF_OK;
+}
 
 // ===========================================================================
 // batched ensembles

@@ -103,6 +103,8 @@ hipError_t launch_noise(int q, int fp64, uint32_t key0, uint32_t key1,
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t key0,
                          uint32_t key1, uint32_t *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream);
+// *p = v by a one-thread kernel (no memset node when captured)
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t stream);
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
                               hipStream_t stream);
 

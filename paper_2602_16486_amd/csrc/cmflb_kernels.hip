@@ -829,6 +829,10 @@ __global__ void k_zero_i64(int64_t *p, int64_t n) {
   if (k < n) p[k] = 0;
 }
 
+__global__ void k_set_i64(int64_t *p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // structure factor (amortized diagnostic): fields, |FFT|^2 accumulation and
 // deterministic shell binning
@@ -1553,6 +1557,11 @@ hipError_t launch_vel_hist(int q, int storage, const ConvParams &cp, const void 
                        static_cast<const S *>(buf), c, dims, nbins, xmax, counts);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, stream, p, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t stream) {
