@@ -197,7 +197,8 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, R &z0,
 template <>
 __device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b,
                                                   float &z0, float &z1) {
-  const float u1 = (float)((a >> 8) + 1u) * 0x1p-24f;  // (0, 1], exact
+  // ((a >> 8) + 1) 2^-24 as one multiply-add of exact operands (exact)
+  const float u1 = __builtin_fmaf((float)(a >> 8), 0x1p-24f, 0x1p-24f);  // (0, 1]
   const float u2 = (float)(b >> 8) * 0x1p-24f;         // [0, 1), exact
   const float r =
       __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u1));
@@ -399,9 +400,19 @@ __host__ __device__ __forceinline__ int64_t pop_row_offset(int i, int64_t row,
 template <typename S, typename R>
 struct Store;
 
+// Each Store<S, R> also converts between the compute type and the stored
+// bits (from_bits / to_bits, the same arithmetic as load / store), for the
+// buffer-addressed accesses of the single-lattice step (buf_load, buf_store).
 template <typename R>
 struct Store<double, R> {
   static constexpr bool scaled = false;
+  using bits_t = unsigned long long;
+  __device__ __forceinline__ static R from_bits(bits_t b, float) {
+    return (R)__longlong_as_double((long long)b);
+  }
+  __device__ __forceinline__ static bits_t to_bits(R v, float) {
+    return (bits_t)__double_as_longlong((double)v);
+  }
   template <bool NT = false>
   __device__ __forceinline__ static R load(const double *p, float) {
     return (R)cmf_ld<NT>(p);
@@ -415,6 +426,9 @@ struct Store<double, R> {
 template <typename R>
 struct Store<float, R> {
   static constexpr bool scaled = false;
+  using bits_t = unsigned int;
+  __device__ __forceinline__ static R from_bits(bits_t b, float) { return (R)__uint_as_float(b); }
+  __device__ __forceinline__ static bits_t to_bits(R v, float) { return __float_as_uint((float)v); }
   template <bool NT = false>
   __device__ __forceinline__ static R load(const float *p, float) {
     return (R)cmf_ld<NT>(p);
@@ -428,6 +442,13 @@ struct Store<float, R> {
 template <typename R>
 struct Store<__half, R> {
   static constexpr bool scaled = true;
+  using bits_t = unsigned short;
+  __device__ __forceinline__ static R from_bits(bits_t b, float scale) {
+    return (R)__builtin_fmaf(__half2float(__ushort_as_half(b)), scale, 0.0f);
+  }
+  __device__ __forceinline__ static bits_t to_bits(R v, float iscale) {
+    return __half_as_ushort(__float2half_rn((float)v * iscale));
+  }
   template <bool NT = false>
   __device__ __forceinline__ static R load(const __half *p, float scale) {
     const unsigned short bits =
@@ -447,6 +468,16 @@ struct Store<__half, R> {
 template <typename R>
 struct Store<__hip_bfloat16, R> {
   static constexpr bool scaled = true;
+  using bits_t = unsigned short;
+  __device__ __forceinline__ static R from_bits(bits_t b, float scale) {
+    return (R)(__uint_as_float(((unsigned int)b) << 16) * scale);
+  }
+  __device__ __forceinline__ static bits_t to_bits(R v, float iscale) {
+    const __hip_bfloat16 h = __float2bfloat16((float)v * iscale);
+    unsigned short bits;
+    __builtin_memcpy(&bits, &h, sizeof(bits));
+    return bits;
+  }
   template <bool NT = false>
   __device__ __forceinline__ static R load(const __hip_bfloat16 *p,
                                            float scale) {
@@ -463,5 +494,52 @@ struct Store<__hip_bfloat16, R> {
     cmf_st<NT>(bits, reinterpret_cast<unsigned short *>(p));
   }
 };
+
+// ---------------------------------------------------------------------------
+// Buffer-resource accesses (gfx9 MUBUF): address = resource base + scalar
+// offset (soffset) + vector offset (voffset), all in bytes, the resource
+// covering `bytes` bytes (at most 4 GiB).  The per-lane part of a
+// population row access is then one 32-bit offset shared by every row with
+// the same x shift, and the row offsets are scalar, so a site's 2 Q accesses
+// take no vector address arithmetic.  NT selects the non-temporal policy.
+// ---------------------------------------------------------------------------
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const S *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0, (int)bytes,
+                                           kRsrcWord3);
+}
+
+template <typename S, bool NT>
+__device__ __forceinline__ typename Store<S, float>::bits_t buf_load(__amdgpu_buffer_rsrc_t r,
+                                                                     uint32_t voff, uint32_t soff) {
+  constexpr int aux = NT ? 2 : 0;
+  if constexpr (sizeof(S) == 2) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, aux);
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, aux);
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, aux);
+    return (unsigned long long)v[0] | ((unsigned long long)v[1] << 32);
+  }
+}
+
+template <typename S, bool NT>
+__device__ __forceinline__ void buf_store(typename Store<S, float>::bits_t b,
+                                          __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  constexpr int aux = NT ? 2 : 0;
+  if constexpr (sizeof(S) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(b, r, (int)voff, (int)soff, aux);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(b, r, (int)voff, (int)soff, aux);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    u2 v;
+    v[0] = (unsigned int)b;
+    v[1] = (unsigned int)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, aux);
+  }
+}
 
 }  // namespace cmf

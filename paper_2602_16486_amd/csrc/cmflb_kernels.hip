@@ -549,6 +549,57 @@ __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
   }
 }
 
+// Buffer-addressed forms of load_site / store_site for the single-lattice
+// step (BUF): one resource per source plane z - c_z (its Q ny rows of nx
+// values, below 4 GiB), the row of population i of source row y - c_y as a
+// scalar byte offset, and one vector byte offset per x shift.
+template <class L, typename S, typename R, bool NT_C0>
+__device__ __forceinline__ void load_site_buf(R *d, const S *__restrict__ src,
+                                              const float *scale, int nx, int ny,
+                                              int nz, int x, int y, int z) {
+  using ST = Store<S, R>;
+  constexpr uint32_t B = sizeof(S);
+  const int64_t plane = (int64_t)ny * L::Q * nx;
+  const uint32_t pbytes = (uint32_t)(plane * B);
+  __amdgpu_buffer_rsrc_t rs[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+    rs[b] = make_rsrc(src + (int64_t)zs * plane, pbytes);
+  }
+  const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1) * B, (uint32_t)x * B,
+                          (uint32_t)(x == 0 ? nx - 1 : x - 1) * B};
+  uint32_t ys[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ys[a] = (uint32_t)wrap_sub(y, a - 1, ny);
+  const uint32_t rowb = (uint32_t)nx * B;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const uint32_t soff = (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)i) * rowb;
+    const float sc = scale[weight_class<L>(i)];
+    if (NT_C0 && L::cx[i] == 0)
+      d[i] = ST::from_bits(buf_load<S, true>(rs[L::cz[i] + 1], xs[1], soff), sc);
+    else
+      d[i] = ST::from_bits(buf_load<S, false>(rs[L::cz[i] + 1], xs[L::cx[i] + 1], soff), sc);
+  }
+}
+
+template <class L, typename S, typename R, bool NT>
+__device__ __forceinline__ void store_site_buf(const R *d, S *__restrict__ dst,
+                                               const float *iscale, int nx, int ny, int x,
+                                               int y, int z) {
+  using ST = Store<S, R>;
+  constexpr uint32_t B = sizeof(S);
+  const int64_t plane = (int64_t)ny * L::Q * nx;
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(dst + (int64_t)z * plane, (uint32_t)(plane * B));
+  const uint32_t rowb = (uint32_t)nx * B;
+  const uint32_t blk = (uint32_t)y * (uint32_t)L::Q;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    buf_store<S, NT>(ST::to_bits(d[i], iscale[weight_class<L>(i)]), r, (uint32_t)x * B,
+                     (blk + (uint32_t)i) * rowb);
+}
+
 struct TileXY {
   int x, y, z;
 };
@@ -562,7 +613,9 @@ __device__ __forceinline__ TileXY tile_coords(int tile, int nxb, int ny, int bx)
 // ONE: the grid has one workgroup per tile (every thread processes at most
 // one site, and its statistics go to the block reduction as compute-type
 // values); otherwise workgroups stride over the tiles and accumulate in FP64.
-template <class L, typename S, typename R, bool GENERAL, bool NT, bool ONE>
+// BUF: buffer-addressed population accesses (every z plane of the buffer
+// below 4 GiB); otherwise 64-bit addresses.
+template <class L, typename S, typename R, bool GENERAL, bool NT, bool ONE, bool BUF>
 __global__ __launch_bounds__(kMaxBlock) void k_step(
     const S *__restrict__ src, S *__restrict__ dst, const StepParams<R> p,
     const int64_t *__restrict__ step_ptr, int step_off, double *__restrict__ partials) {
@@ -577,11 +630,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
     const TileXY c = tile_coords(tile, p.nxb, ny, BX);
     if (c.x < nx) {
       R d[Q];
-      load_site<L, S, R, false, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+      if constexpr (BUF)
+        load_site_buf<L, S, R, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+      else
+        load_site<L, S, R, false, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, (uint32_t)site, step, acc);
-      store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
+      if constexpr (BUF)
+        store_site_buf<L, S, R, NT>(d, dst, p.iscale, nx, ny, c.x, c.y, c.z);
+      else
+        store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
     }
     if constexpr (ONE) break;
   }
@@ -1181,26 +1240,40 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <class L, typename S, typename R, bool G, bool NT>
-hipError_t step_one(const void *params, const void *src, void *dst,
-                    const int64_t *step_ptr, int step_off, double *partials, int grid,
-                    int block, hipStream_t stream) {
-  const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
+template <class L, typename S, typename R, bool G, bool NT, bool BUF>
+hipError_t step_shape(const StepParams<R> &p, const void *src, void *dst,
+                      const int64_t *step_ptr, int step_off, double *partials, int grid,
+                      int block, hipStream_t stream) {
   // one workgroup per tile: per-site statistics (measured faster for D2Q9,
   // 4096^2 FP32 0.218 -> 0.205 ms; 1-2% slower for the 3-D lattices, whose
   // kernels then keep the FP64 accumulation)
   if constexpr (L::Q == 9) {
     if (grid >= p.ntiles) {
-      hipLaunchKernelGGL((k_step<L, S, R, G, NT, true>), dim3(p.ntiles), dim3(block),
+      hipLaunchKernelGGL((k_step<L, S, R, G, NT, true, BUF>), dim3(p.ntiles), dim3(block),
                          acc_lds_bytes<R>(block), stream, static_cast<const S *>(src),
                          static_cast<S *>(dst), p, step_ptr, step_off, partials);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_step<L, S, R, G, NT, false>), dim3(grid), dim3(block),
+  hipLaunchKernelGGL((k_step<L, S, R, G, NT, false, BUF>), dim3(grid), dim3(block),
                      acc_lds_bytes<double>(block), stream, static_cast<const S *>(src),
                      static_cast<S *>(dst), p, step_ptr, step_off, partials);
   return hipGetLastError();
+}
+
+template <class L, typename S, typename R, bool G, bool NT>
+hipError_t step_one(const void *params, const void *src, void *dst,
+                    const int64_t *step_ptr, int step_off, double *partials, int grid,
+                    int block, hipStream_t stream) {
+  const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
+  // buffer-addressed accesses when every z plane (ny Q nx values) of a
+  // population buffer spans less than 4 GiB
+  const bool buf = (int64_t)p.ny * L::Q * p.nx * (int64_t)sizeof(S) < ((int64_t)1 << 32);
+  if (buf)
+    return step_shape<L, S, R, G, NT, true>(p, src, dst, step_ptr, step_off, partials, grid,
+                                            block, stream);
+  return step_shape<L, S, R, G, NT, false>(p, src, dst, step_ptr, step_off, partials, grid,
+                                           block, stream);
 }
 
 template <class L, typename S, typename R>
