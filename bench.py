@@ -113,7 +113,7 @@ def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
         "glups": glups,
         "kernel_ms": kernel_ms,
         "kernel_gbs": bytes_per_site(storage, q) * n / (kernel_ms * 1e-3) / 1e9,
-        "u2_over_kT": float(u2.mean() * RHO0 / KT),
+        "u2_over_kT": float(u2.mean() * RHO0 / KT) if KT > 0 else None,
         "u2_series": u2,
         "nonfinite": float(st[:, 11].sum()),
     }
@@ -154,6 +154,30 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
             half = st[len(st) // 2:]
             dims = 2 if r["q"] == 9 else 3
             ratios.append(float(half[:, 8:8 + dims].sum(axis=1).mean() / (dims * n) * r["rho0"] / r["kT"]))
+    # time split by lattice type: the D2Q9 and the D3Q27 replicas of the
+    # manifest as ensembles of their own, in the tile shape just used
+    split = {}
+    for q in (9, 27):
+        part = [r for r in manifest if r["q"] == q]
+        with Ensemble(part, storage="f32", stream=stream.cuda_stream, series_capacity=64) as sub:
+            sub.set_tiles(*tiles)
+            sub.step(4)
+            split[f"d2q9_ms" if q == 9 else "d3q27_ms"] = sub.profile_steps(10) / 10
+    # lanes a tile leaves idle: a tile of replica r holds the whole rows that
+    # fit in spt x 256 lanes (or spt x 256 sites of a longer row)
+    idle = {}
+    for q in (9, 27):
+        lanes = sites = 0
+        for r in manifest:
+            if r["q"] != q:
+                continue
+            spt = tiles[0] if q == 9 else tiles[1]
+            nx, n = W.shape3(r["shape"])[0], W.n_sites(r["shape"])
+            tl = spt * 256
+            ts = tl // nx * nx if nx <= tl else tl
+            lanes += -(-n // ts) * tl
+            sites += n
+        idle["d2q9" if q == 9 else "d3q27"] = 1.0 - sites / lanes
     # the same replicas one at a time
     seq_ms = 0.0
     nseq = 20
@@ -173,6 +197,8 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
         "kernel_ms": kernel_ms, "sites": total, "replicas": len(manifest),
         "tiles_sites_per_thread": {"d2q9": tiles[0], "3d": tiles[1]},
         "bytes_per_step": sum(W.n_sites(r["shape"]) * 2 * r["q"] * 4 for r in manifest),
+        "split_kernel_ms": split,
+        "idle_lane_fraction": idle,
         "sequential_single_replica_glups": total / (seq_ms * 1e-3) / 1e9,
         "speedup_vs_sequential": seq_ms / ms,
         "u2_over_kT_median": float(np.median(ratios)),
@@ -219,6 +245,7 @@ def cpu_baseline():
 
 
 def main():
+    global KT
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -227,6 +254,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--kT", type=float, default=KT,
+                    help="thermal energy of the timed lattices (profiling aid: 0 switches the "
+                         "noise off; the headline workload is 1e-4)")
     ap.add_argument("--d3q19", default="f32,f16",
                     help="storages of the D3Q19 256^3 lines (empty: none)")
     args = ap.parse_args()
@@ -234,6 +264,7 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    KT = args.kT
     if args.steps < 1 or args.warmup < 0:
         print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
@@ -297,13 +328,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "D3Q27 256^3 periodic, rest start, rho0=1, tau=0.8, kT=1e-4, Philox seed 1; "
+            "workload": f"D3Q27 256^3 periodic, rest start, rho0=1, tau=0.8, kT={KT:g}, Philox seed 1; "
                         "FP32 deviation storage, FP32 collide, FP64 per-step statistics",
             "lattice": "D3Q27", "box": list(SHAPE), "storage": "f32",
             "bytes_per_site_step": bytes_per_site("f32"),
             "launch": list(main_run["launch"]),
             # environment variables that select launch or tile shapes (never results)
-            "env": {k: os.environ[k] for k in ("CMFLB_TUNE_CACHE", "CMF_ENSEMBLE_SPT9",
+            "env": {k: os.environ[k] for k in ("CMFLB_TUNE_CACHE", "CMF_BLOCK", "CMF_GRID", "CMF_ENSEMBLE_SPT9",
                                                "CMF_ENSEMBLE_SPT27") if k in os.environ},
         },
         "timing": {

@@ -150,8 +150,9 @@ int env_int(const char *name, int dflt, int lo, int hi) {
 
 namespace {
 
-// FP64 per-mode constants of one descriptor: rates, weights, noise
-// amplitudes (eq. phi_general without the local sqrt(rho)), storage scales.
+// FP64 per-mode constants of one descriptor: rates, weights, mode noise
+// factors amp_v = I~_v sqrt(Lambda_v (2 - Lambda_v) b_v) (eq. phi_general
+// is phi_v = sqrt(rho kT / c_s^2) amp_v), storage scales.
 struct ModeConstants {
   double lambda[27], w[27], amp[27];
   float scale[27];
@@ -176,7 +177,7 @@ void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
   mode_norms(q, b);
   for (int v = 0; v < q; ++v) {
     const double lv = mc.lambda[v];
-    mc.amp[v] = v >= first_noisy(q) ? sqrt(desc->kT * lv * (2.0 - lv) * b[v] / kCs2) : 0.0;
+    mc.amp[v] = v >= first_noisy(q) ? sqrt(lv * (2.0 - lv) * b[v]) : 0.0;
   }
   for (int i = 0; i < q; ++i) {
     if (desc->storage == kF16 || desc->storage == kBF16) {

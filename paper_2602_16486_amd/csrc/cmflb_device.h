@@ -183,39 +183,43 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1,
   return U4{c0, c1, c2, c3};
 }
 
-// Box-Muller pair from two Philox words (a -> radius, b -> angle).
+// Box-Muller pair from two Philox words (a -> radius, b -> angle), times a
+// scale s: (z0, z1) = s (r cos theta, r sin theta).  The FP32 and FP64 step
+// kernels pass the site's noise amplitude, which then costs one multiply
+// per pair of modes instead of one per mode.
 template <typename R>
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, R &z0,
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, R s, R &z0,
                                            R &z1);
 
 // FP32: the hardware transcendentals.  v_log_f32 gives log2, so
-// -2 ln(u1) = -2 ln(2) log2(u1); v_sin_f32 / v_cos_f32 take their argument
-// in revolutions, so sin(2 pi u2) is v_sin_f32(u2) with no range reduction.
-// Over all 2^24 possible u1 and u2 the radius is within 4.9e-7 and sine and
-// cosine within 1.3e-7 of the exact values (exhaustive check on gfx950),
-// i.e. |eta_fp32 - eta| <= 1.2e-6.
+// r = sqrt(-2 ln u1) = sqrt(2 ln 2) sqrt(-log2 u1); v_sin_f32 / v_cos_f32
+// take their argument in revolutions, so sin(2 pi u2) is v_sin_f32(u2) with
+// no range reduction.  Over all 2^24 possible u1 and u2 the radius
+// sqrt(-2 ln 2 log2 u1) is within 4.9e-7 and sine and cosine within 1.3e-7
+// of the exact values (exhaustive check on gfx950), i.e.
+// |eta_fp32 - eta| <= 1.2e-6; the form used here rounds the factor
+// sqrt(2 ln 2) s separately (one more rounding of r, 6e-8 relative).
 template <>
-__device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b,
+__device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b, float s,
                                                   float &z0, float &z1) {
   // ((a >> 8) + 1) 2^-24 as one multiply-add of exact operands (exact)
   const float u1 = __builtin_fmaf((float)(a >> 8), 0x1p-24f, 0x1p-24f);  // (0, 1]
   const float u2 = (float)(b >> 8) * 0x1p-24f;         // [0, 1), exact
-  const float r =
-      __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u1));
+  const float r = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u1)) * (s * 1.17741002f);
   z0 = r * __builtin_amdgcn_cosf(u2);
   z1 = r * __builtin_amdgcn_sinf(u2);
 }
 
 template <>
-__device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b,
+__device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b, double s,
                                                    double &z0, double &z1) {
   const double u1 = (double)((a >> 8) + 1u) * 0x1p-24;
   const double u2 = (double)(b >> 8) * 0x1p-24;
-  const double r = sqrt(-2.0 * log(u1));
-  double s, c;
-  sincospi(2.0 * u2, &s, &c);
-  z0 = r * c;
-  z1 = r * s;
+  const double r = sqrt(-2.0 * log(u1)) * s;
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  z0 = r * cs;
+  z1 = r * sn;
 }
 
 // The NNOISE normals of one site and step, eta[n] for mode FIRST_NOISY + n.
@@ -224,10 +228,12 @@ __device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b,
 // are distinct, and steps below 2^32 keep the plain (site, step, replica,
 // block) counter.  The step is wave-uniform, so its two words cost scalar
 // operations only.
+// scale: every normal comes out multiplied by it (1 for the normals
+// themselves).
 template <class L, typename R>
 __device__ __forceinline__ void site_normals(uint32_t site, uint64_t step,
                                              uint32_t replica, uint32_t k0,
-                                             uint32_t k1, R *eta) {
+                                             uint32_t k1, R scale, R *eta) {
   const uint32_t step_lo = (uint32_t)step;
   const uint32_t blk_hi = (uint32_t)(step >> 32) << 8;
 #pragma unroll
@@ -235,12 +241,12 @@ __device__ __forceinline__ void site_normals(uint32_t site, uint64_t step,
     const U4 w = philox4x32_10(site, step_lo, replica, (uint32_t)blk | blk_hi, k0, k1);
     const int n0 = 4 * blk;
     R a, b;
-    box_muller<R>(w.x, w.y, a, b);
+    box_muller<R>(w.x, w.y, scale, a, b);
     if (n0 < L::NNOISE) eta[n0] = a;
     if (n0 + 1 < L::NNOISE) eta[n0 + 1] = b;
     if (n0 + 2 < L::NNOISE) {
       R c, d;
-      box_muller<R>(w.z, w.w, c, d);
+      box_muller<R>(w.z, w.w, scale, c, d);
       eta[n0 + 2] = c;
       if (n0 + 3 < L::NNOISE) eta[n0 + 3] = d;
     }

@@ -12,8 +12,9 @@ constexpr int kPartStride = 12;// doubles per block partial
 constexpr int kSeriesStride = 12;
 constexpr int kMaxBlock = 256;
 // statistics partials beyond this count are first summed by up to
-// kMaxLevel2 workgroups (second-level rows)
-constexpr int kLevel2Threshold = 1024;
+// kMaxLevel2 workgroups (second-level rows); 256 rows per workgroup, one per
+// thread (65536 one-tile partials: 256 workgroups, one per CU)
+constexpr int kLevel2Threshold = 256;
 constexpr int kMaxLevel2 = 256;
 
 // Parameters of one lattice as the step kernels see them (kernel argument,
@@ -24,8 +25,11 @@ struct StepParams {
   int32_t ntiles;           // nxb * ny * nz
   int32_t noise;            // kT > 0
   R rho0;
-  R amp[27];   // I~_v sqrt(kT Lambda_v (2 - Lambda_v) b_v / c_s^2)
-  R amp1;      // sqrt(kT / c_s^2): amp_v = amp1 sqrt(b_v) when Lambda_v = 1
+  // phi_v = sqrt(rho) amp1 amp_v (eq. phi_general): amp_v = I~_v
+  // sqrt(Lambda_v (2 - Lambda_v) b_v) (sqrt(b_v) when Lambda_v = 1) and
+  // amp1 = sqrt(kT / c_s^2)
+  R amp[27];
+  R amp1;
   R oml[27];   // 1 - Lambda_v
   R lam[27];   // Lambda_v
   // storage scale s and 1 / s of each weight class |c_i|^2 = 0..3 (s_i

@@ -81,6 +81,11 @@ struct SiteStats {
   }
 };
 
+// 1 / rho: the hardware reciprocal in FP32 (within 1 ulp; the FP32 path's
+// error budget is set by its storage rounding), a division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename R>
 __device__ __forceinline__ bool finite4(R a, R b, R c, R d) {
   return __builtin_isfinite(a) && __builtin_isfinite(b) &&
@@ -147,20 +152,26 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
     }
   }
   const R rho = p.rho0 + drho;
-  const R irho = R(1) / rho;
+  const R irho = recip(rho);
   const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
 
   acc.record(drho, jx, jy, jz, ux, uy, uz, finite4(rho, ux, uy, uz));
 
-  // step 2: normals of the noisy modes
+  // step 2: normals of the noisy modes.  phi_v = a1 amp_v with the site's
+  // noise scale a1 = sqrt(rho kT / c_s^2) (eq. phi_general with the local
+  // rho) and the mode factors amp_v = sqrt(Lambda_v (2 - Lambda_v) b_v).
+  // The issue-bound 16-bit kernels (LEAN) draw the plain normals, which do
+  // not wait for the loaded populations, and scale each mode by a1 amp_v;
+  // the others draw them times a1 (one multiply per pair of modes instead
+  // of one per mode: FP32 256^3 step 1.3 % faster)
+  const R a1 = p.amp1 * sqrt(rho);
   R eta[L::NNOISE];
   if (p.noise) {
-    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, eta);
+    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, LEAN ? R(1) : a1, eta);
   } else {
 #pragma unroll
     for (int n = 0; n < L::NNOISE; ++n) eta[n] = R(0);
   }
-  const R sq = sqrt(rho);  // phi_v = sqrt(rho) amp_v (local rho)
 
   R t[L::NT];
   if constexpr (!GENERAL) {
@@ -175,21 +186,20 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       t[1] = R(0);
       t[3] = R(0);
       t[9] = R(0);
-      const R a1 = p.amp1 * sq;
 #pragma unroll
       for (int n = 0; n < L::NNOISE; ++n) {
         const int v = L::FIRST_NOISY + n;
         R val;
         if (v == 7)
-          val = p.oml[7] * k7 + p.amp[7] * sq * eta[n];
+          val = p.oml[7] * k7 + (LEAN ? a1 * p.amp[7] : p.amp[7]) * eta[n];
         else if (v == 8)
-          val = p.oml[8] * k8 + p.amp[8] * sq * eta[n];
+          val = p.oml[8] * k8 + (LEAN ? a1 * p.amp[8] : p.amp[8]) * eta[n];
         else if (v == 9)
-          val = p.oml[9] * k9 + p.amp[9] * sq * eta[n];
+          val = p.oml[9] * k9 + (LEAN ? a1 * p.amp[9] : p.amp[9]) * eta[n];
         else if constexpr (LEAN)
           val = a1 * R(sqrt_norm<L>(v)) * eta[n];
         else
-          val = p.amp[v] * sq * eta[n];
+          val = p.amp[v] * eta[n];
         t[L::mode_pos[v]] = val;
       }
     } else {
@@ -206,11 +216,10 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       // k_4 = r_4 - rho (u_x^2 - u_y^2), k_5 = r_5 - rho u_x u_y (Sec. 2.2)
       const R k4 = sd - (jx * ux - jy * uy);
       const R k5 = sxy - jx * uy;
-      const R a1 = p.amp1 * sq;
-      auto amp_eta = [&](int v, R e) { return LEAN ? a1 * R(sqrt_norm<L>(v)) * e : p.amp[v] * sq * e; };
+      auto amp_eta = [&](int v, R e) { return LEAN ? a1 * R(sqrt_norm<L>(v)) * e : p.amp[v] * e; };
       const R k3s = amp_eta(3, eta[0]);
-      const R k4s = p.oml[4] * k4 + p.amp[4] * sq * eta[1];
-      const R k5s = p.oml[5] * k5 + p.amp[5] * sq * eta[2];
+      const R k4s = p.oml[4] * k4 + (LEAN ? a1 * p.amp[4] : p.amp[4]) * eta[1];
+      const R k5s = p.oml[5] * k5 + (LEAN ? a1 * p.amp[5] : p.amp[5]) * eta[2];
       t[0] = rho;
       t[1] = R(0);
       t[3] = R(0);
@@ -238,7 +247,7 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       for (int v = 0; v < 27; ++v) {
         R val = p.oml[v] * k[v];
         if (v == 0) val += p.lam[0] * rho;
-        if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+        if (v >= L::FIRST_NOISY) val += (LEAN ? a1 * p.amp[v] : p.amp[v]) * eta[v - L::FIRST_NOISY];
         t[L::mode_pos[v]] = val;
       }
     } else {
@@ -257,7 +266,7 @@ __device__ __forceinline__ void collide_tensor(R *d, const P &p,
       for (int v = 0; v < 9; ++v) {
         R val = p.oml[v] * k[v];
         if (v == 0) val += p.lam[0] * rho;
-        if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+        if (v >= L::FIRST_NOISY) val += (LEAN ? a1 * p.amp[v] : p.amp[v]) * eta[v - L::FIRST_NOISY];
         ks[v] = val;
       }
       t[0] = ks[0];
@@ -300,19 +309,19 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
   d3q19::raw_moments(d, r);
   const R drho = r[0], jx = r[1], jy = r[2], jz = r[3];
   const R rho = p.rho0 + drho;
-  const R irho = R(1) / rho;
+  const R irho = recip(rho);
   const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
 
   acc.record(drho, jx, jy, jz, ux, uy, uz, finite4(rho, ux, uy, uz));
 
+  const R a1 = p.amp1 * sqrt(rho);  // as in collide_tensor
   R eta[L::NNOISE];
   if (p.noise) {
-    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, eta);
+    site_normals<L, R>(site, step, p.replica, p.key0, p.key1, LEAN ? R(1) : a1, eta);
   } else {
 #pragma unroll
     for (int n = 0; n < L::NNOISE; ++n) eta[n] = R(0);
   }
-  const R sq = sqrt(rho);
 
   R k[19];
   if constexpr (!GENERAL) {
@@ -321,21 +330,20 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
     k[1] = R(0);
     k[2] = R(0);
     k[3] = R(0);
-    const R a1 = p.amp1 * sq;
 #pragma unroll
     for (int n = 0; n < L::NNOISE; ++n) {
       const int v = L::FIRST_NOISY + n;
       R val;
       if (v == 7)
-        val = p.oml[7] * k7 + p.amp[7] * sq * eta[n];
+        val = p.oml[7] * k7 + (LEAN ? a1 * p.amp[7] : p.amp[7]) * eta[n];
       else if (v == 8)
-        val = p.oml[8] * k8 + p.amp[8] * sq * eta[n];
+        val = p.oml[8] * k8 + (LEAN ? a1 * p.amp[8] : p.amp[8]) * eta[n];
       else if (v == 9)
-        val = p.oml[9] * k9 + p.amp[9] * sq * eta[n];
+        val = p.oml[9] * k9 + (LEAN ? a1 * p.amp[9] : p.amp[9]) * eta[n];
       else if constexpr (LEAN)
         val = a1 * R(sqrt_norm<L>(v)) * eta[n];
       else
-        val = p.amp[v] * sq * eta[n];
+        val = p.amp[v] * eta[n];
       k[v] = val;
     }
   } else {
@@ -346,7 +354,7 @@ __device__ __forceinline__ void collide_d3q19(R *d, const P &p, uint32_t site,
     for (int v = 0; v < 19; ++v) {
       R val = p.oml[v] * r[v];
       if (v == 0) val += p.lam[0] * rho;
-      if (v >= L::FIRST_NOISY) val += p.amp[v] * sq * eta[v - L::FIRST_NOISY];
+      if (v >= L::FIRST_NOISY) val += (LEAN ? a1 * p.amp[v] : p.amp[v]) * eta[v - L::FIRST_NOISY];
       k[v] = val;
     }
   }
@@ -448,104 +456,54 @@ __device__ __forceinline__ int wrap_sub(int a, int c, int n) {
   return r;
 }
 
-// Element at a 32-bit byte offset from a wave-uniform base pointer: the
-// scalar-base + 32-bit vector-offset form of the global memory instructions.
-template <typename T>
-__device__ __forceinline__ T *at_byte(T *base, uint32_t boff) {
-  return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff);
-}
-template <typename T>
-__device__ __forceinline__ const T *at_byte(const T *base, uint32_t boff) {
-  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
-}
-
 // Pull the Q populations of site (x, y, z) of a box (nx, ny, nz) whose
-// buffer starts at src: f_i(x) <- f*_i(x - c_i), periodic.
-//
-// LANE_ROWS = false: y and z are wave-uniform (one lattice row per tile), so
-// the row part of every address is scalar.  (Addressing each population row
-// from its own scalar base measured 4% slower here than 64-bit vector
-// addresses: the 27 bases spill scalar registers.)
-// LANE_ROWS = true: every lane may sit in another row (ensemble tiles); the
-// whole offset inside the buffer is one 32-bit byte count from the uniform
-// buffer base (the buffer is below 4 GiB, checked at creation), which saves
-// the per-lane 64-bit address arithmetic.
+// buffer starts at src: f_i(x) <- f*_i(x - c_i), periodic, with 64-bit
+// addresses (the single-lattice step when a z plane of the buffer spans
+// 4 GiB or more; otherwise load_site_buf).  y and z are wave-uniform (one
+// lattice row per tile), so the row part of every address is scalar.
 // NT_C0: non-temporal loads for the populations with c_x = 0, only when
 // every population row is a whole number of cache lines (then tiles, which
 // start at a row or at a multiple of 256 sites of a row, never share a
 // line of such a row).
-template <class L, typename S, typename R, bool LANE_ROWS, bool NT_C0 = false>
+template <class L, typename S, typename R, bool NT_C0 = false>
 __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
                                           const float *scale, int nx, int ny,
                                           int nz, int x, int y, int z) {
   using ST = Store<S, R>;
   const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1), (uint32_t)x,
                           (uint32_t)(x == 0 ? nx - 1 : x - 1)};
-  if constexpr (!LANE_ROWS) {
-    int64_t srow[3][3];
+  int64_t srow[3][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int ys = wrap_sub(y, a - 1, ny);
-        const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
-        srow[a][b] = (int64_t)ys + (int64_t)ny * zs;
-      }
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
-      const float sc = scale[weight_class<L>(i)];
-      // (the condition is a compile-time constant once the loop is unrolled)
-      if (NT_C0 && L::cx[i] == 0)
-        d[i] = ST::template load<true>(base + xs[1], sc);
-      else
-        d[i] = ST::template load<false>(base + xs[L::cx[i] + 1], sc);
+    for (int b = 0; b < 3; ++b) {
+      const int ys = wrap_sub(y, a - 1, ny);
+      const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+      srow[a][b] = (int64_t)ys + (int64_t)ny * zs;
     }
-  } else {
-    constexpr uint32_t B = sizeof(S);
-    const uint32_t unx = (uint32_t)nx, uny = (uint32_t)ny;
-    uint32_t sblk[3][3];  // first element of the Q-row block of each source row
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const uint32_t ys = (uint32_t)wrap_sub(y, a - 1, ny);
-        const uint32_t zs = L::D == 3 ? (uint32_t)wrap_sub(z, b - 1, nz) : (uint32_t)z;
-        sblk[a][b] = (ys + uny * zs) * (uint32_t)L::Q * unx;
-      }
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const uint32_t e = sblk[L::cy[i] + 1][L::cz[i] + 1] + (uint32_t)i * unx + xs[L::cx[i] + 1];
-      const float sc = scale[weight_class<L>(i)];
-      if (NT_C0 && L::cx[i] == 0)
-        d[i] = ST::template load<true>(at_byte(src, e * B), sc);
-      else
-        d[i] = ST::template load<false>(at_byte(src, e * B), sc);
-    }
+  for (int i = 0; i < L::Q; ++i) {
+    const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
+    const float sc = scale[weight_class<L>(i)];
+    // (the condition is a compile-time constant once the loop is unrolled)
+    if (NT_C0 && L::cx[i] == 0)
+      d[i] = ST::template load<true>(base + xs[1], sc);
+    else
+      d[i] = ST::template load<false>(base + xs[L::cx[i] + 1], sc);
   }
 }
 
 // Write the Q post-collision populations of site x of lattice row `row`
-// (same two addressing forms as load_site; NT selects the store kind).
-template <class L, typename S, typename R, bool LANE_ROWS, bool NT>
+// (64-bit addresses, as load_site; NT selects the store kind).
+template <class L, typename S, typename R, bool NT>
 __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
                                            const float *iscale, int nx, int x,
                                            int64_t row) {
   using ST = Store<S, R>;
-  if constexpr (!LANE_ROWS) {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      S *base = dst + pop_row_offset<L::Q>(i, row, nx);
-      ST::template store<NT>(base + (uint32_t)x, d[i], iscale[weight_class<L>(i)]);
-    }
-  } else {
-    constexpr uint32_t B = sizeof(S);
-    const uint32_t unx = (uint32_t)nx;
-    const uint32_t blk = (uint32_t)row * (uint32_t)L::Q * unx + (uint32_t)x;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-      ST::template store<NT>(at_byte(dst, (blk + (uint32_t)i * unx) * B), d[i],
-                             iscale[weight_class<L>(i)]);
+  for (int i = 0; i < L::Q; ++i) {
+    S *base = dst + pop_row_offset<L::Q>(i, row, nx);
+    ST::template store<NT>(base + (uint32_t)x, d[i], iscale[weight_class<L>(i)]);
   }
 }
 
@@ -633,14 +591,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
       if constexpr (BUF)
         load_site_buf<L, S, R, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       else
-        load_site<L, S, R, false, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+        load_site<L, S, R, NT>(d, src, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
       const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
       const int site = (int)(c.x + nx * row);
       collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, (uint32_t)site, step, acc);
       if constexpr (BUF)
         store_site_buf<L, S, R, NT>(d, dst, p.iscale, nx, ny, c.x, c.y, c.z);
       else
-        store_site<L, S, R, false, NT>(d, dst, p.iscale, nx, c.x, row);
+        store_site<L, S, R, NT>(d, dst, p.iscale, nx, c.x, row);
     }
     if constexpr (ONE) break;
   }
@@ -854,7 +812,7 @@ __global__ __launch_bounds__(256) void k_noise(uint32_t key0, uint32_t key1,
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   R eta[L::NNOISE];
-  site_normals<L, R>((uint32_t)(site0 + k), step, replica, key0, key1, eta);
+  site_normals<L, R>((uint32_t)(site0 + k), step, replica, key0, key1, R(1), eta);
   for (int v = 0; v < L::Q; ++v)
     out[k * L::Q + v] =
         v < L::FIRST_NOISY ? 0.0 : (double)eta[v - L::FIRST_NOISY];
@@ -1141,12 +1099,17 @@ __device__ __forceinline__ uint32_t udiv_invariant(uint32_t n, uint32_t m, uint3
   return (t + ((n - t) >> (sh & 255u))) >> (sh >> 8);
 }
 
+// One site of an ensemble replica whose populations the resources rs / rd
+// cover (the replica's q N values, below 4 GiB): every lane may sit in
+// another row, so the vector byte offset carries the row block and the x
+// shift, and the scalar offset the population row i nx.
 template <class L, typename S, typename R, bool GENERAL, bool NT>
-__device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
-                                              S *__restrict__ dst,
+__device__ __forceinline__ void ensemble_site(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rd,
                                               const ReplicaParams<R> &p,
                                               int64_t s, uint64_t step,
                                               Acc &acc) {
+  using ST = Store<S, R>;
+  constexpr uint32_t B = sizeof(S);
   const uint32_t nx = (uint32_t)p.nx, ny = (uint32_t)p.ny;
   const uint32_t us = (uint32_t)s;
   const uint32_t row = udiv_invariant(us, p.div_nx, p.sh_nx);
@@ -1154,10 +1117,33 @@ __device__ __forceinline__ void ensemble_site(const S *__restrict__ src,
   const uint32_t zr = udiv_invariant(row, p.div_ny, p.sh_ny);
   const int y = (int)(row - zr * ny);
   const int z = (int)zr;
+  const uint32_t xs[3] = {(uint32_t)(x == p.nx - 1 ? 0 : x + 1), (uint32_t)x,
+                          (uint32_t)(x == 0 ? p.nx - 1 : x - 1)};
+  uint32_t sblk[3][3];  // first element of the Q-row block of each source row
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const uint32_t ys = (uint32_t)wrap_sub(y, a - 1, p.ny);
+      const uint32_t zs = L::D == 3 ? (uint32_t)wrap_sub(z, b - 1, p.nz) : (uint32_t)z;
+      sblk[a][b] = (ys + ny * zs) * (uint32_t)L::Q * nx;
+    }
+  const uint32_t rowb = nx * B;
   R d[L::Q];
-  load_site<L, S, R, true, NT>(d, src + p.offset, p.scale, p.nx, p.ny, p.nz, x, y, z);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const uint32_t voff = (sblk[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1]) * B;
+    const float sc = p.scale[weight_class<L>(i)];
+    if (NT && L::cx[i] == 0)
+      d[i] = ST::from_bits(buf_load<S, true>(rs, voff, (uint32_t)i * rowb), sc);
+    else
+      d[i] = ST::from_bits(buf_load<S, false>(rs, voff, (uint32_t)i * rowb), sc);
+  }
   collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);
-  store_site<L, S, R, true, NT>(d, dst + p.offset, p.iscale, p.nx, x, (int64_t)row);
+  const uint32_t voff = (row * (uint32_t)L::Q * nx + (uint32_t)x) * B;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    buf_store<S, NT>(ST::to_bits(d[i], p.iscale[weight_class<L>(i)]), rd, voff, (uint32_t)i * rowb);
 }
 
 // Workgroups are handed to the XCDs round-robin by id and every XCD has its
@@ -1189,20 +1175,24 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
   const int64_t t0 = (int64_t)(tile - p.tile0) * p.tsites;
   const int64_t s0 = t0 + threadIdx.x;
   const int64_t end = t0 + p.tsites < p.nsites ? t0 + p.tsites : p.nsites;
+  // the replica's populations, below 4 GiB (checked at creation)
+  const uint32_t bytes = (uint32_t)((int64_t)p.q * p.nsites * (int64_t)sizeof(S));
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + p.offset, bytes);
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + p.offset, bytes);
   if (p.q == 27) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D3Q27, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q27, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
     }
   } else if (p.q == 19) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D3Q19, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q19, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
     }
   } else {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D2Q9, S, R, GENERAL, NT>(src, dst, p, s, step, acc);
+      if (s < end) ensemble_site<D2Q9, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
     }
   }
   block_store_acc_shuffle(acc, partials + (int64_t)tile * kPartStride);

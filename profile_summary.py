@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402  (kernel_source_hash, constants)
 
-STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false, true, false>"
+STEP_KERNEL = "void cmf::k_step<cmf::D3Q27, float, float, false, true, false, true>"
 COPY_KERNEL = "cmf::cmf_stream_copy_kernel"
 N = 256 ** 3
 ALG_BYTES = 2 * 27 * 4 * N
@@ -187,12 +187,12 @@ def ensemble_summary(outdir):
 CMD_VAR = ("rocprofv3 --kernel-trace --stats -d out/prof_var -o var --output-format csv "
            "-- python3 bench.py --steps 100 --warmup 32 --no-cpu --no-tune --no-ensemble")
 VARIANTS = [  # (kernel name prefix, label, q, bytes per stored value, bench.py entry)
-    ("void cmf::k_step<cmf::D3Q27, float, float, false, true, false>", "D3Q27 FP32", 27, 4, None),
-    ("void cmf::k_step<cmf::D3Q27, __half, float, false, true, false>", "D3Q27 FP16", 27, 2, ("variants", "f16")),
-    ("void cmf::k_step<cmf::D3Q27, __hip_bfloat16, float, false, true, false>", "D3Q27 BF16", 27, 2,
+    ("void cmf::k_step<cmf::D3Q27, float, float, false, true, false, true>", "D3Q27 FP32", 27, 4, None),
+    ("void cmf::k_step<cmf::D3Q27, __half, float, false, true, false, true>", "D3Q27 FP16", 27, 2, ("variants", "f16")),
+    ("void cmf::k_step<cmf::D3Q27, __hip_bfloat16, float, false, true, false, true>", "D3Q27 BF16", 27, 2,
      ("variants", "bf16")),
-    ("void cmf::k_step<cmf::D3Q19, float, float, false, true, false>", "D3Q19 FP32", 19, 4, ("lattices", "d3q19_f32")),
-    ("void cmf::k_step<cmf::D3Q19, __half, float, false, true, false>", "D3Q19 FP16", 19, 2, ("lattices", "d3q19_f16")),
+    ("void cmf::k_step<cmf::D3Q19, float, float, false, true, false, true>", "D3Q19 FP32", 19, 4, ("lattices", "d3q19_f32")),
+    ("void cmf::k_step<cmf::D3Q19, __half, float, false, true, false, true>", "D3Q19 FP16", 19, 2, ("lattices", "d3q19_f16")),
 ]
 
 
