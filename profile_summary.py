@@ -311,8 +311,120 @@ def valu_summary(outdir):
     print("\n".join(lines))
 
 
+CMD_VALU0 = CMD_VALU.replace("prof_valu", "prof_valu0").replace("-o valu", "-o valu0").replace(
+    "--no-ensemble", "--no-ensemble --kT 0")
+CMD_ASM = ("/opt/rocm/lib/llvm/bin/clang++ -x hip --offload-arch=gfx950 --offload-device-only -O3 -std=c++17 "
+           "-ffp-contract=on -I include -Xclang -target-feature -Xclang -packed-fp32-ops -S "
+           "paper_2602_16486_amd/csrc/cmflb_kernels.hip -o out/kernels.s")
+# opcode classes of the static budget
+CLASSES = [
+    ("Philox4x32-10 (64-bit products, 3-input xor)", ("v_mad_u64_u32", "v_bitop3_b32")),
+    ("Box-Muller (log2, sqrt, sin, cos; word to float)", ("v_log_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
+                                                           "v_cvt_f32_u32", "v_lshrrev_b32")),
+    ("16-bit loads and stores (scale and convert)", ("v_fma_mix_f32", "v_fma_mixlo_f16", "v_cvt_pk_bf16_f32")),
+    ("statistics (FP64 accumulation)", ("v_add_f64", "v_cvt_f64_f32")),
+]
+
+
+def _kernel_ops(asm_path, mangled_prefix):
+    """Opcode counts of one kernel function in the assembly listing."""
+    import collections
+    lines = open(asm_path).read().split("\n")
+    start = next(i for i, l in enumerate(lines) if l.startswith(mangled_prefix) and l.rstrip().endswith(":")
+                 or (l.startswith(mangled_prefix) and ": " in l))
+    end = next(i for i in range(start + 1, len(lines)) if lines[i].strip().startswith(".Lfunc_end"))
+    ops = collections.Counter()
+    for l in lines[start + 1:end]:
+        t = l.strip()
+        if not t or t.startswith((".", ";")) or t.endswith(":"):
+            continue
+        ops[t.split()[0].split("_e32")[0].split("_e64")[0]] += 1
+    return ops
+
+
+BUDGET_KERNELS = [  # (label, mangled-name prefix, counter label in VARIANTS)
+    ("D3Q27 FP16", "_ZN3cmf6k_stepINS_5D3Q27E6__halffLb0ELb1ELb0ELb1E", "D3Q27 FP16"),
+    ("D3Q27 BF16", "_ZN3cmf6k_stepINS_5D3Q27E14__hip_bfloat16fLb0ELb1ELb0ELb1E", "D3Q27 BF16"),
+    ("D3Q27 FP32", "_ZN3cmf6k_stepINS_5D3Q27EffLb0ELb1ELb0ELb1E", "D3Q27 FP32"),
+]
+
+
+def _valu_per_site(path):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        for prefix, label, q, sbytes, _ in VARIANTS:
+            if r["Kernel_Name"].startswith(prefix) and r["Counter_Name"] == "SQ_INSTS_VALU":
+                vals.setdefault(label, []).append(float(r["Counter_Value"]))
+    return {k: statistics.median(v) * 64 / N for k, v in vals.items()}
+
+
+def valu_budget(outdir):
+    """profiles/k_step_valu_budget_256cube.md: VALU instructions per site of
+    the step kernels with the noise on (kT = 1e-4) and off (kT = 0), measured,
+    and the static instruction mix of each kernel by class."""
+    on_path = os.path.join(outdir, "prof_valu", "valu_counter_collection.csv")
+    off_path = os.path.join(outdir, "prof_valu0", "valu0_counter_collection.csv")
+    asm = os.path.join(outdir, "kernels.s")
+    if not (os.path.exists(on_path) and os.path.exists(off_path) and os.path.exists(asm)):
+        return
+    on, off = _valu_per_site(on_path), _valu_per_site(off_path)
+    lines = [
+        "# VALU budget per site of the step kernels at 256^3 — rocprofv3 counters and static instruction mix",
+        "",
+        "Workload: as in `k_step_valu_256cube.md` (D3Q27 and D3Q19 256^3, rest start, rho0=1, tau=0.8, "
+        "Philox seed 1), once with kT = 1e-4 (the benchmark) and once with kT = 0 (noise off: the kernels "
+        "skip the normals, everything else is the same work).",
+        "",
+        "Commands (repository root on a machine with an MI355X, after `cd /tmp && export TMPDIR=/tmp`; "
+        "the assembly listing needs no GPU):",
+        "",
+        "    CMFLB_TUNE_CACHE=out/tune.txt python3 bench.py --no-cpu --no-ensemble > out/tune_run.json",
+        "    " + CMD_VALU,
+        "    " + CMD_VALU0,
+        "    " + CMD_ASM,
+        "    python profile_summary.py out",
+        "",
+        "## Measured (SQ_INSTS_VALU x 64 / 256^3, median over dispatches)",
+        "",
+        "| kernel | VALU instr / site, kT = 1e-4 | kT = 0 | noise (difference) |",
+        "|---|---|---|---|",
+    ]
+    for _, label, _, _, _ in VARIANTS:
+        if label in on and label in off:
+            lines.append(f"| {label} | {on[label]:.0f} | {off[label]:.0f} | {on[label] - off[label]:.0f} "
+                         f"({(on[label] - off[label]) / on[label] * 100:.0f} %) |")
+    lines += ["", "## Static instruction mix of each kernel function (gfx950 assembly of the sources)", "",
+              "Whole function: the per-tile loop body plus a prologue and the block reduction of the "
+              "statistics at the end (a few percent); the 16-bit and FP32 step kernels run 8 and 1 tiles per "
+              "workgroup in the benchmark's launch shapes.", ""]
+    head = "| class | " + " | ".join(k[0] for k in BUDGET_KERNELS) + " |"
+    lines += [head, "|---|" + "---|" * len(BUDGET_KERNELS)]
+    counts = [_kernel_ops(asm, k[1]) for k in BUDGET_KERNELS]
+    totals = [sum(v for o, v in c.items() if o.startswith("v_")) for c in counts]
+    used = [0] * len(counts)
+    for name, ops in CLASSES:
+        row = []
+        for j, c in enumerate(counts):
+            n = sum(c.get(o, 0) for o in ops)
+            used[j] += n
+            row.append(str(n))
+        lines.append(f"| {name} | " + " | ".join(row) + " |")
+    lines.append("| collision, moments, addresses and the rest | " +
+                 " | ".join(str(t - u) for t, u in zip(totals, used)) + " |")
+    lines.append("| all VALU instructions | " + " | ".join(str(t) for t in totals) + " |")
+    lines += ["", "Philox4x32-10 needs 10 rounds of two 32 x 32 -> 64-bit products per block and six blocks "
+              "per D3Q27 site (the first round's products are shared between the blocks); the Box-Muller "
+              "transform takes four hardware transcendentals per pair of normals.  Both are fixed by the noise "
+              "definition, so the 16-bit kernels, which issue a VALU instruction every cycle, are bound by them.",
+              ""]
+    with open(os.path.join(ROOT, "profiles", "k_step_valu_budget_256cube.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     main(sys.argv[1] if len(sys.argv) > 1 else "out")
     ensemble_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
     variants_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
     valu_summary(sys.argv[1] if len(sys.argv) > 1 else "out")
+    valu_budget(sys.argv[1] if len(sys.argv) > 1 else "out")
