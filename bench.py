@@ -163,19 +163,17 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
             sub.set_tiles(*tiles)
             sub.step(4)
             split[f"d2q9_ms" if q == 9 else "d3q27_ms"] = sub.profile_steps(10) / 10
-    # lanes a tile leaves idle: a tile of replica r holds the whole rows that
-    # fit in spt x 256 lanes (or spt x 256 sites of a longer row)
+    # lanes the tiles leave idle: a tile is spt x 256 consecutive sites of
+    # one replica, so only the last tile of a replica is ragged
     idle = {}
     for q in (9, 27):
         lanes = sites = 0
         for r in manifest:
             if r["q"] != q:
                 continue
-            spt = tiles[0] if q == 9 else tiles[1]
-            nx, n = W.shape3(r["shape"])[0], W.n_sites(r["shape"])
-            tl = spt * 256
-            ts = tl // nx * nx if nx <= tl else tl
-            lanes += -(-n // ts) * tl
+            tl = (tiles[0] if q == 9 else tiles[1]) * 256
+            n = W.n_sites(r["shape"])
+            lanes += -(-n // tl) * tl
             sites += n
         idle["d2q9" if q == 9 else "d3q27"] = 1.0 - sites / lanes
     # the same replicas one at a time

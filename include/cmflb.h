@@ -365,11 +365,13 @@ typedef struct cmf_ensemble cmf_ensemble;
 
 /* Create an ensemble of n >= 1 replicas from n descriptors (validated as in
  * cmf_create; storage and flags must agree; series_capacity of descs[0]
- * applies to all; each replica's q x N populations must take below 4 GiB
- * in the storage type).  All replicas start at rest at step 0.  Allocates
- * two population arenas holding every replica, the replica records, the
- * tile map and the statistics buffers.  Errors: CMF_EINVAL, CMF_ENOMEM,
- * CMF_EHIP. */
+ * applies to all; each replica's q arrays of N rounded up to 64 values
+ * must take below 4 GiB in the storage type).  All replicas start at rest
+ * at step 0.  Allocates two population arenas holding every replica (one
+ * array per population of each replica, unlike the row-interleaved layout
+ * of a cmf_lattice; read and write states with the calls below), the
+ * replica records, the tile map and the statistics buffers.  Errors:
+ * CMF_EINVAL, CMF_ENOMEM, CMF_EHIP. */
 int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream,
                         cmf_ensemble **out);
 
@@ -382,8 +384,8 @@ int cmf_ensemble_info(cmf_ensemble *ens, int32_t *n_replicas,
 
 /* Tile shape of the ensemble step kernel: one workgroup of 256 threads per
  * tile, each thread up to spt sites (spt9 for D2Q9 replicas, spt3d for
- * D3Q19 and D3Q27 replicas); a tile holds as many whole rows of its replica
- * as fit in spt x 256 sites, or spt x 256 sites of a longer row.  Defaults
+ * D3Q19 and D3Q27 replicas); a tile is spt x 256 consecutive sites of its
+ * replica (x fastest), the last tile of a replica ragged.  Defaults
  * 3 and 1 (environment variables CMF_ENSEMBLE_SPT9 and CMF_ENSEMBLE_SPT27
  * override them at creation). */
 typedef struct {

@@ -736,6 +736,7 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
   L->cp.nx = desc->nx;
   L->cp.ny = desc->ny;
   L->cp.nz = desc->nz;
+  L->cp.pitch = 0;
   L->cp.rho0 = desc->rho0;
   for (int i = 0; i < q; ++i) {
     L->cp.w[i] = L->w[i];
@@ -1487,6 +1488,7 @@ struct cmf_ensemble {
     cmf_desc desc;
     int64_t N = 0;
     int64_t offset = 0;  // elements
+    int64_t pitch = 0;   // elements per population array: N rounded up to 64
     int tile0 = 0, ntiles = 0, spt = 1, tsites = 0;
     ConvParams cp;
   };
@@ -1494,7 +1496,6 @@ struct cmf_ensemble {
   int storage = 1;
   uint32_t flags = 0;
   bool general = false;
-  bool nt_stores = true;  // every replica's population rows are whole cache lines
   bool own_stream = false;
   hipStream_t stream = nullptr;
   std::vector<Rep> reps;
@@ -1544,6 +1545,7 @@ void fill_replica(const cmf_desc &d, const ModeConstants &mc, const cmf_ensemble
   p.ntiles = rp.ntiles;
   p.spt = rp.spt;
   p.tsites = rp.tsites;
+  p.pitch = (int32_t)rp.pitch;
   invariant_divisor((uint32_t)d.nx, &p.div_nx, &p.sh_nx);
   invariant_divisor((uint32_t)d.ny, &p.div_ny, &p.sh_ny);
   p.noise = d.kT > 0.0 ? 1 : 0;
@@ -1585,7 +1587,7 @@ double *ens_partials_buf(const cmf_ensemble *E, int b) {
 
 // One direct step (as enqueue_one_step of a lattice).
 int ens_enqueue_step(cmf_ensemble *E) {
-  HIP_TRY(launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
+  HIP_TRY(launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
                                E->arena[E->parity], E->arena[1 - E->parity], E->step_dev, 0,
                                ens_partials_buf(E, 0), E->stream));
   HIP_TRY(launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, 0), E->series,
@@ -1600,7 +1602,7 @@ struct EnsembleRun {
   int parity;
   hipError_t operator()(int j, hipStream_t s) const {
     const int b = parity ^ (j & 1);
-    return launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep,
+    return launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep,
                                 E->ntiles, E->arena[b], E->arena[b ^ 1], E->step_dev, j,
                                 ens_partials_buf(E, j & 1), s);
   }
@@ -1638,9 +1640,8 @@ void *ens_replica_buffer(cmf_ensemble *E, int index) {
 }
 
 // Tile the replicas, 3-D replicas first, then D2Q9, each in creation order:
-// a tile of a replica takes as many whole rows as fit in spt x
-// kEnsembleBlock sites, spt = spt9 (D2Q9) or spt3d (D3Q19, D3Q27), or that
-// many sites when one row is longer.  Uploads the tile map and the replica
+// a tile of a replica is spt x kEnsembleBlock consecutive sites, spt = spt9
+// (D2Q9) or spt3d (D3Q19, D3Q27), the last tile of a replica ragged.  Uploads the tile map and the replica
 // records, grows the tile map and the partial-sum buffers when needed and
 // drops captured graphs.  The stream must be idle.
 int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
@@ -1652,9 +1653,7 @@ int ens_build_tiles(cmf_ensemble *E, int spt9, int spt3d) {
       if ((pass == 0) != (q != 9)) continue;
       tile0[r] = (int)tile_rep.size();
       spt[r] = q == 9 ? spt9 : spt3d;
-      const int64_t lanes = (int64_t)spt[r] * kEnsembleBlock;
-      const int64_t nx = E->reps[r].desc.nx;
-      tsites[r] = (int)(nx <= lanes ? lanes / nx * nx : lanes);
+      tsites[r] = spt[r] * kEnsembleBlock;
       const int64_t n = (E->reps[r].N + tsites[r] - 1) / tsites[r];
       if ((int64_t)tile_rep.size() + n >= ((int64_t)1 << 31))
         return fail(CMF_EINVAL, "ensemble has too many tiles");
@@ -1720,9 +1719,10 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     if (rc != CMF_OK) return fail(rc, "replica %d: %s", r, g_last_error.c_str());
     if (descs[r].storage != descs[0].storage) return fail(CMF_EINVAL, "replica %d: storage differs from replica 0", r);
     if (descs[r].flags != descs[0].flags) return fail(CMF_EINVAL, "replica %d: flags differ from replica 0", r);
-    // ensemble tiles address a replica's buffer with 32-bit byte offsets
-    const int64_t bytes = (int64_t)descs[r].q * descs[r].nx * descs[r].ny * descs[r].nz *
-                          storage_bytes(descs[r].storage);
+    // ensemble tiles address a replica's buffer (q arrays of N rounded up
+    // to 64) with 32-bit byte offsets
+    const int64_t n_pad = ((int64_t)descs[r].nx * descs[r].ny * descs[r].nz + 63) / 64 * 64;
+    const int64_t bytes = (int64_t)descs[r].q * n_pad * storage_bytes(descs[r].storage);
     if (bytes >= ((int64_t)1 << 32))
       return fail(CMF_EINVAL, "replica %d: %lld population bytes; an ensemble member holds below 4 GiB",
                   r, (long long)bytes);
@@ -1743,13 +1743,14 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     rp.desc.lambda = nullptr;
     rp.N = (int64_t)descs[r].nx * descs[r].ny * descs[r].nz;
     rp.offset = offset;
-    offset += ((int64_t)descs[r].q * rp.N + 63) / 64 * 64;
+    rp.pitch = (rp.N + 63) / 64 * 64;
+    offset += (int64_t)descs[r].q * rp.pitch;
     mode_constants(&descs[r], mcs[r]);
     if (mcs[r].general) E->general = true;
-    if (((int64_t)descs[r].nx * storage_bytes(descs[r].storage)) % kLineBytes != 0) E->nt_stores = false;
     rp.cp.nx = descs[r].nx;
     rp.cp.ny = descs[r].ny;
     rp.cp.nz = descs[r].nz;
+    rp.cp.pitch = rp.pitch;
     rp.cp.rho0 = descs[r].rho0;
     for (int i = 0; i < descs[r].q; ++i) {
       rp.cp.w[i] = mcs[r].w[i];
@@ -1998,7 +1999,7 @@ int cmf_ensemble_profile_steps(cmf_ensemble *E, int64_t nsteps, double *kernel_m
   for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
     e = hipEventRecord(ev[2 * s], E->stream);
     if (e == hipSuccess)
-      e = launch_ensemble_step(E->storage, E->general, E->nt_stores, E->d_reps, E->d_tile_rep, E->ntiles,
+      e = launch_ensemble_step(E->storage, E->general, E->d_reps, E->d_tile_rep, E->ntiles,
                                E->arena[E->parity], E->arena[1 - E->parity], E->step_dev, 0,
                                ens_partials_buf(E, 0), E->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], E->stream);

@@ -48,8 +48,9 @@ struct ReplicaParams {
   int32_t nsites, tile0, ntiles, noise;
   int64_t offset;  // element offset of the replica's populations in an arena
   uint32_t key0, key1, replica;
-  int32_t spt;     // sites per thread: a tile has at most spt x kEnsembleBlock sites
-  int32_t tsites;  // sites per tile: the whole rows that fit, or spt x kEnsembleBlock
+  int32_t spt;     // sites per thread: a tile has spt x kEnsembleBlock sites
+  int32_t tsites;  // sites per tile, spt x kEnsembleBlock (the last one ragged)
+  int32_t pitch;   // elements from population i to i + 1: nsites rounded up to 64
   // exact division of a site index by nx and of a row index by ny with a
   // multiplier m and shifts s1 | s2 << 8 (see udiv_invariant)
   uint32_t div_nx, div_ny, sh_nx, sh_ny;
@@ -61,9 +62,12 @@ struct ReplicaParams {
   float scale[4], iscale[4];  // per weight class, as in StepParams
 };
 
-// Parameters of the state conversion kernels (FP64 always).
+// Parameters of the state conversion kernels (FP64 always).  pitch = 0:
+// the row-interleaved layout of a single lattice; pitch > 0: one array per
+// population, population i starting at element i pitch (ensemble replicas).
 struct ConvParams {
   int32_t nx, ny, nz;
+  int64_t pitch;
   double rho0;
   double w[27];
   float scale[27], iscale[27];
@@ -150,7 +154,7 @@ constexpr int kLineBytes = 128;
 constexpr int kXcds = 8;
 // adjacent ensemble tiles kept on one XCD
 constexpr int kXcdChunk = 32;
-hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
+hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
                                 const int64_t *step_ptr, int step_off, double *partials,

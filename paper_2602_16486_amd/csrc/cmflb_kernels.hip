@@ -668,10 +668,12 @@ __global__ __launch_bounds__(256) void k_finalize(
 // ---------------------------------------------------------------------------
 // state conversion kernels (FP64 arithmetic)
 // ---------------------------------------------------------------------------
-// element offset of population i at site s in the population buffer
+// element offset of population i at site s in the population buffer (the
+// row-interleaved layout, or one array per population when cp.pitch > 0)
 template <int Q>
 __device__ __forceinline__ int64_t pop_site_offset(const ConvParams &cp, int i,
                                                    int64_t s) {
+  if (cp.pitch > 0) return (int64_t)i * cp.pitch + s;
   return pop_row_offset<Q>(i, s / cp.nx, cp.nx) + s % cp.nx;
 }
 
@@ -1082,12 +1084,16 @@ __global__ __launch_bounds__(256) void k_vel_hist(const ConvParams cp,
 // ---------------------------------------------------------------------------
 // batched ensemble: one launch per step over the tiles of every replica
 // ---------------------------------------------------------------------------
-// A tile is a run of consecutive sites (x fastest) of one replica: as many
-// whole lattice rows as fit in spt x kEnsembleBlock sites, or that many
-// sites of a longer row.  Whole rows keep every cache line of a row, and of
-// the population rows stored around it, inside one workgroup; the lanes
-// beyond the tile's rows idle.  The replica, and with it the lattice type,
-// is uniform per workgroup.
+// Layout of a replica: one array per population (population i of site s at
+// element i pitch + s, pitch = the site count rounded up to 64), unlike the
+// row-interleaved single lattice.  Replica rows have any length, so rows
+// seldom start on a cache line; per-population arrays keep the stores of a
+// tile whole, aligned cache lines whatever the row length (64 consecutive
+// sites are 128 B or more in every storage type), so they are written
+// non-temporally, and only the loads of shifted rows straddle lines.
+// A tile is spt x kEnsembleBlock consecutive sites (x fastest) of one
+// replica, the last tile of a replica ragged: lanes idle only there.  The
+// replica, and with it the lattice type, is uniform per workgroup.
 // Replicas are listed 3-D first (heavier tiles dispatched first).
 // n / d for any 32-bit n by a multiply-high and two shifts, with m and
 // s1 | s2 << 8 precomputed for the divisor d (Granlund and Montgomery,
@@ -1100,10 +1106,11 @@ __device__ __forceinline__ uint32_t udiv_invariant(uint32_t n, uint32_t m, uint3
 }
 
 // One site of an ensemble replica whose populations the resources rs / rd
-// cover (the replica's q N values, below 4 GiB): every lane may sit in
-// another row, so the vector byte offset carries the row block and the x
-// shift, and the scalar offset the population row i nx.
-template <class L, typename S, typename R, bool GENERAL, bool NT>
+// cover (q pitch values, below 4 GiB): the vector byte offset carries the
+// source site, the scalar offset the population array i pitch.  The rest
+// population is read at the site itself, an aligned stream read once, so
+// it is loaded non-temporally too.
+template <class L, typename S, typename R, bool GENERAL>
 __device__ __forceinline__ void ensemble_site(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rd,
                                               const ReplicaParams<R> &p,
                                               int64_t s, uint64_t step,
@@ -1119,31 +1126,31 @@ __device__ __forceinline__ void ensemble_site(__amdgpu_buffer_rsrc_t rs, __amdgp
   const int z = (int)zr;
   const uint32_t xs[3] = {(uint32_t)(x == p.nx - 1 ? 0 : x + 1), (uint32_t)x,
                           (uint32_t)(x == 0 ? p.nx - 1 : x - 1)};
-  uint32_t sblk[3][3];  // first element of the Q-row block of each source row
+  uint32_t srow[3][3];  // first site of each source row
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const uint32_t ys = (uint32_t)wrap_sub(y, a - 1, p.ny);
       const uint32_t zs = L::D == 3 ? (uint32_t)wrap_sub(z, b - 1, p.nz) : (uint32_t)z;
-      sblk[a][b] = (ys + ny * zs) * (uint32_t)L::Q * nx;
+      srow[a][b] = (ys + ny * zs) * nx;
     }
-  const uint32_t rowb = nx * B;
+  const uint32_t popb = (uint32_t)p.pitch * B;
   R d[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const uint32_t voff = (sblk[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1]) * B;
+    const uint32_t voff = (srow[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1]) * B;
     const float sc = p.scale[weight_class<L>(i)];
-    if (NT && L::cx[i] == 0)
-      d[i] = ST::from_bits(buf_load<S, true>(rs, voff, (uint32_t)i * rowb), sc);
+    if (L::cx[i] == 0 && L::cy[i] == 0 && L::cz[i] == 0)
+      d[i] = ST::from_bits(buf_load<S, true>(rs, voff, (uint32_t)i * popb), sc);
     else
-      d[i] = ST::from_bits(buf_load<S, false>(rs, voff, (uint32_t)i * rowb), sc);
+      d[i] = ST::from_bits(buf_load<S, false>(rs, voff, (uint32_t)i * popb), sc);
   }
   collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);
-  const uint32_t voff = (row * (uint32_t)L::Q * nx + (uint32_t)x) * B;
+  const uint32_t voff = us * B;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    buf_store<S, NT>(ST::to_bits(d[i], p.iscale[weight_class<L>(i)]), rd, voff, (uint32_t)i * rowb);
+    buf_store<S, true>(ST::to_bits(d[i], p.iscale[weight_class<L>(i)]), rd, voff, (uint32_t)i * popb);
 }
 
 // Workgroups are handed to the XCDs round-robin by id and every XCD has its
@@ -1161,7 +1168,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return ((k / kXcdChunk) * kXcds + j) * kXcdChunk + k % kXcdChunk;
 }
 
-template <typename S, typename R, bool GENERAL, bool NT>
+template <typename S, typename R, bool GENERAL>
 __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
     const S *__restrict__ src, S *__restrict__ dst,
     const ReplicaParams<R> *__restrict__ reps, const int32_t *__restrict__ tile_rep,
@@ -1175,24 +1182,24 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
   const int64_t t0 = (int64_t)(tile - p.tile0) * p.tsites;
   const int64_t s0 = t0 + threadIdx.x;
   const int64_t end = t0 + p.tsites < p.nsites ? t0 + p.tsites : p.nsites;
-  // the replica's populations, below 4 GiB (checked at creation)
-  const uint32_t bytes = (uint32_t)((int64_t)p.q * p.nsites * (int64_t)sizeof(S));
+  // the replica's population arrays, below 4 GiB (checked at creation)
+  const uint32_t bytes = (uint32_t)((int64_t)p.q * p.pitch * (int64_t)sizeof(S));
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + p.offset, bytes);
   const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + p.offset, bytes);
   if (p.q == 27) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D3Q27, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q27, S, R, GENERAL>(rs, rd, p, s, step, acc);
     }
   } else if (p.q == 19) {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D3Q19, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
+      if (s < end) ensemble_site<D3Q19, S, R, GENERAL>(rs, rd, p, s, step, acc);
     }
   } else {
     for (int j = 0; j < p.spt; ++j) {
       const int64_t s = s0 + (int64_t)j * kEnsembleBlock;
-      if (s < end) ensemble_site<D2Q9, S, R, GENERAL, NT>(rs, rd, p, s, step, acc);
+      if (s < end) ensemble_site<D2Q9, S, R, GENERAL>(rs, rd, p, s, step, acc);
     }
   }
   block_store_acc_shuffle(acc, partials + (int64_t)tile * kPartStride);
@@ -1490,28 +1497,24 @@ hipError_t launch_stream_copy(const void *src, void *dst, size_t n16,
   return hipGetLastError();
 }
 
-hipError_t launch_ensemble_step(int storage, bool general, bool nt, const void *reps,
+hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
                                 const int64_t *step_ptr, int step_off, double *partials,
                                 hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  auto go = [&](auto stt, auto rt, auto gt, auto ntt) {
+  auto go = [&](auto stt, auto rt, auto gt) {
     using S = typename decltype(stt)::type;
     using R = typename decltype(rt)::type;
     constexpr bool G = decltype(gt)::value;
-    constexpr bool NT = decltype(ntt)::value;
-    hipLaunchKernelGGL((k_ensemble_step<S, R, G, NT>), dim3(ntiles), dim3(kEnsembleBlock), 0,
+    hipLaunchKernelGGL((k_ensemble_step<S, R, G>), dim3(ntiles), dim3(kEnsembleBlock), 0,
                        stream, static_cast<const S *>(src), static_cast<S *>(dst),
                        static_cast<const ReplicaParams<R> *>(reps), tile_rep, step_ptr,
                        step_off, partials);
     return hipGetLastError();
   };
-  auto by_nt = [&](auto stt, auto rt, auto gt) {
-    return nt ? go(stt, rt, gt, std::true_type{}) : go(stt, rt, gt, std::false_type{});
-  };
   auto by_general = [&](auto stt, auto rt) {
-    return general ? by_nt(stt, rt, std::true_type{}) : by_nt(stt, rt, std::false_type{});
+    return general ? go(stt, rt, std::true_type{}) : go(stt, rt, std::false_type{});
   };
   switch (storage) {
     case kF64: return by_general(Tag<double>{}, Tag<double>{});
