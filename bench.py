@@ -85,11 +85,11 @@ def time_steps(lat, steps, stream, torch):
     return start.elapsed_time(end) / steps
 
 
-def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q):
+def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q, in_place=False):
     from paper_2602_16486_amd import Lattice
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
     with Lattice(q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
-                 stream=stream.cuda_stream, series_capacity=8192) as lat:
+                 stream=stream.cuda_stream, series_capacity=8192, in_place=in_place) as lat:
         if tune:
             lat.autotune(steps_per_trial=10)  # untimed; state restored
         launch = lat.launch
@@ -257,6 +257,9 @@ def main():
                          "noise off; the headline workload is 1e-4)")
     ap.add_argument("--d3q19", default="f32,f16",
                     help="storages of the D3Q19 256^3 lines (empty: none)")
+    ap.add_argument("--in-place", default="f32",
+                    help="storages of the D3Q27 256^3 lines with in-place (AA) streaming, one "
+                         "population buffer (empty: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -306,6 +309,27 @@ def main():
             "u2_over_kT": r["u2_over_kT"],
         }
         log(f"D3Q19 {storage}: {r['glups']:.2f} GLUPS, kernel {r['kernel_gbs']:.0f} GB/s")
+
+    in_place = {}
+    for storage in [s for s in args.in_place.split(",") if s]:
+        log(f"timing in-place {storage}")
+        r = time_storage(storage, args.steps, args.warmup, stream, torch, tune=not args.no_tune,
+                         in_place=True)
+        ref = main_run if storage == "f32" else None
+        entry = {
+            "value": r["glups"], "ms_per_step": r["ms_per_step"],
+            "median_ms_per_step": r["median_ms_per_step"], "kernel_ms": r["kernel_ms"],
+            "kernel_gbs": r["kernel_gbs"], "frac_hbm": r["kernel_gbs"] / PEAK_HBM_GBS,
+            "launch": list(r["launch"]), "bytes_per_site": bytes_per_site(storage),
+            "population_bytes": Q * n * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage],
+            "u2_over_kT": r["u2_over_kT"],
+        }
+        if ref is not None:
+            m = min(len(r["u2_series"]), len(ref["u2_series"]))
+            a, c = r["u2_series"][:m], ref["u2_series"][:m]
+            entry["u2_rel_diff_vs_pull"] = float(np.abs(a - c).max() / np.abs(c).mean())
+        in_place[storage] = entry
+        log(f"in-place {storage}: {r['glups']:.2f} GLUPS, kernel {r['kernel_ms']:.4f} ms")
 
     copy_bytes = Q * n * 4  # one FP32 population buffer: the step's footprint
     copy_ms = _lib.stream_copy(copy_bytes, reps=5)
@@ -359,6 +383,7 @@ def main():
         "u2_over_kT": main_run["u2_over_kT"],
         "variants": variants,
         "lattices": lattices,
+        "in_place": in_place,
     }
     if not args.no_ensemble:
         log("timing the batched ensemble (256 D2Q9 + 64 D3Q27 replicas)")

@@ -26,6 +26,7 @@ CMF_EUNSUPPORTED = -5
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 FLAG_NO_GRAPH = 1
 FLAG_NO_STATS = 2
+FLAG_IN_PLACE = 4
 
 # columns of one statistics row (same order as cmf_moments)
 STAT_COLUMNS = ("step", "sum_rho", "sum_jx", "sum_jy", "sum_jz", "sum_ux", "sum_uy", "sum_uz",

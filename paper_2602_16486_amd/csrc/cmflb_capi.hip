@@ -293,6 +293,7 @@ struct cmf_lattice {
   int storage = 0;
   bool general = false;
   bool nt_stores = true;  // population rows are whole cache lines
+  bool in_place = false;  // AA streaming on one buffer (buf[1] == buf[0])
   bool own_stream = false;
   bool own_bufs = true;  // false: the population buffers belong to the caller
   hipStream_t stream = nullptr;
@@ -397,8 +398,8 @@ bool g_tune_file_loaded = false;
 
 std::string tune_key(const cmf_lattice *L) {
   char b[160];
-  snprintf(b, sizeof b, "dev%d:q%d:s%d:g%d:%dx%dx%d", L->device, L->q, L->storage,
-           L->general ? 1 : 0, L->desc.nx, L->desc.ny, L->desc.nz);
+  snprintf(b, sizeof b, "dev%d:q%d:s%d:g%d:%dx%dx%d%s", L->device, L->q, L->storage,
+           L->general ? 1 : 0, L->desc.nx, L->desc.ny, L->desc.nz, L->in_place ? ":aa" : "");
   return b;
 }
 
@@ -502,13 +503,31 @@ double *partials_buf(const cmf_lattice *L, int b) {
   return L->partials + (size_t)b * kPartStride * L->partials_cap;
 }
 
+// Streaming form of a step that starts from state parity b: the pull from
+// buffer b into buffer 1 - b, or in place the even half of an AA pair from
+// parity 0 (populations at their own sites) and the odd half from parity 1.
+int stream_mode(const cmf_lattice *L, int b) {
+  return !L->in_place ? kStreamPull : b == 0 ? kStreamAAEven : kStreamAAOdd;
+}
+
+// conversion parameters for the current state parity
+ConvParams conv(const cmf_lattice *L) {
+  ConvParams cp = L->cp;
+  cp.layout = !L->in_place ? kLayoutPull : L->parity == 0 ? kLayoutNatural : kLayoutSwapped;
+  return cp;
+}
+
+// the fused step from state parity b, step index *step_dev + off
+hipError_t launch_lattice_step(const cmf_lattice *L, int b, int off, double *partials,
+                               hipStream_t s) {
+  return launch_step(L->q, L->storage, L->general, L->nt_stores, stream_mode(L, b), step_params(L),
+                     L->buf[b], L->buf[b ^ 1], L->step_dev, off, partials, L->grid, L->block, s);
+}
+
 // One direct step: the fused kernel, then its statistics and the step
 // counter on the same stream.
 int enqueue_one_step(cmf_lattice *L) {
-  const void *src = L->buf[L->parity];
-  void *dst = L->buf[1 - L->parity];
-  HIP_TRY(launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst,
-                      L->step_dev, 0, partials_buf(L, 0), L->grid, L->block, L->stream));
+  HIP_TRY(launch_lattice_step(L, L->parity, 0, partials_buf(L, 0), L->stream));
   HIP_TRY(launch_finalize(partials_buf(L, 0), L->nparts, L->level2, L->series, L->cap,
                           L->step_dev, 0, 1, L->mass0,
                           !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream));
@@ -542,9 +561,7 @@ struct LatticeRun {
   cmf_lattice *L;
   int parity;
   hipError_t operator()(int j, hipStream_t s) const {
-    const int b = parity ^ (j & 1);
-    return launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), L->buf[b],
-                       L->buf[b ^ 1], L->step_dev, j, partials_buf(L, j & 1), L->grid, L->block, s);
+    return launch_lattice_step(L, parity ^ (j & 1), j, partials_buf(L, j & 1), s);
   }
 };
 struct LatticeFin {
@@ -575,7 +592,7 @@ void release(cmf_lattice *L) {
   if (L->stream) (void)hipStreamSynchronize(L->stream);
   for (int k = 0; k < 2; ++k) {
     if (L->graph[k]) (void)hipGraphExecDestroy(L->graph[k]);
-    if (L->buf[k] && L->own_bufs) (void)hipFree(L->buf[k]);
+    if (L->buf[k] && L->own_bufs && !(k == 1 && L->buf[1] == L->buf[0])) (void)hipFree(L->buf[k]);
   }
   if (L->partials) (void)hipFree(L->partials);
   if (L->level2) (void)hipFree(L->level2);
@@ -684,14 +701,30 @@ size_t buffer_bytes(const cmf_desc *d) {
   return ((size_t)d->q * d->nx * d->ny * d->nz * storage_bytes(d->storage) + 255) / 256 * 256;
 }
 
+// population buffers of a lattice: one with in-place streaming, else two
+int buffer_count(const cmf_desc *d) { return (d->flags & CMF_FLAG_IN_PLACE) ? 1 : 2; }
+
+// in-place streaming addresses each z plane (ny q nx values) with 32-bit
+// byte offsets
+int check_in_place(const cmf_desc *d) {
+  if (!(d->flags & CMF_FLAG_IN_PLACE)) return CMF_OK;
+  const int64_t plane = (int64_t)d->ny * d->q * d->nx * storage_bytes(d->storage);
+  if (plane >= ((int64_t)1 << 32))
+    return fail(CMF_EUNSUPPORTED, "in-place streaming needs each z plane below 4 GiB (%lld bytes)",
+                (long long)plane);
+  return CMF_OK;
+}
+
 int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext_bytes,
                    cmf_lattice **out) {
   if (!out) return fail(CMF_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate(desc);
   if (rc != CMF_OK) return rc;
+  rc = check_in_place(desc);
+  if (rc != CMF_OK) return rc;
   if (ext) {
-    const size_t need = 2 * buffer_bytes(desc);
+    const size_t need = buffer_count(desc) * buffer_bytes(desc);
     if (reinterpret_cast<uintptr_t>(ext) % 256 != 0)
       return fail(CMF_EINVAL, "external buffer is not 256-byte aligned");
     if (ext_bytes < need)
@@ -719,6 +752,7 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
   mode_constants(desc, mc);
   L->general = mc.general;
   L->nt_stores = ((int64_t)desc->nx * storage_bytes(desc->storage)) % kLineBytes == 0;
+  L->in_place = (desc->flags & CMF_FLAG_IN_PLACE) != 0;
   double amp[27];
   float scale[27];
   for (int v = 0; v < q; ++v) {
@@ -737,6 +771,7 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
   L->cp.ny = desc->ny;
   L->cp.nz = desc->nz;
   L->cp.pitch = 0;
+  L->cp.layout = kLayoutPull;
   L->cp.rho0 = desc->rho0;
   for (int i = 0; i < q; ++i) {
     L->cp.w[i] = L->w[i];
@@ -763,14 +798,15 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
   if (ext) {
     L->own_bufs = false;
     L->buf[0] = ext;
-    L->buf[1] = static_cast<char *>(ext) + bytes;
+    L->buf[1] = L->in_place ? ext : static_cast<char *>(ext) + bytes;
   } else {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < buffer_count(desc); ++k) {
       if (hipMalloc(&L->buf[k], bytes) != hipSuccess) {
         release(L);
         return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
       }
     }
+    if (L->in_place) L->buf[1] = L->buf[0];
   }
   if (hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
       hipMalloc((void **)&L->level2, sizeof(double) * kPartStride * kMaxLevel2) != hipSuccess ||
@@ -820,8 +856,8 @@ int cmf_create_external(const cmf_desc *desc, void *dev_ptr, size_t bytes, void 
 }
 
 size_t cmf_external_bytes(const cmf_desc *desc) {
-  if (validate(desc) != CMF_OK) return 0;
-  return 2 * buffer_bytes(desc);
+  if (validate(desc) != CMF_OK || check_in_place(desc) != CMF_OK) return 0;
+  return buffer_count(desc) * buffer_bytes(desc);
 }
 
 int cmf_destroy(cmf_lattice *L) {
@@ -839,7 +875,7 @@ int cmf_init_equilibrium(cmf_lattice *L, const double *rho, const double *u) {
   hipError_t e = upload_init_fields(L->N, rho, u, &drho, &du);
   if (e == hipSuccess) {
     L->parity = 0;
-    e = launch_init_eq(L->q, L->storage, L->cp, drho, du, L->buf[0], L->stream);
+    e = launch_init_eq(L->q, L->storage, conv(L), drho, du, L->buf[0], L->stream);
   }
   if (e == hipSuccess) e = launch_zero_i64(L->step_dev, 1, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -858,7 +894,7 @@ int cmf_set_populations(cmf_lattice *L, const double *f) {
   if (hipMalloc((void **)&df, bytes) != hipSuccess)
     return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
   hipError_t e = hipMemcpy(df, f, bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_set_state(L->q, L->storage, L->cp, df, L->buf[L->parity], L->stream);
+  if (e == hipSuccess) e = launch_set_state(L->q, L->storage, conv(L), df, L->buf[L->parity], L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   (void)hipFree(df);
   if (e != hipSuccess) return fail(CMF_EHIP, "set_populations failed: %s", hipGetErrorString(e));
@@ -872,7 +908,7 @@ int cmf_get_populations(cmf_lattice *L, double *f) {
   const size_t bytes = sizeof(double) * L->q * L->N;
   if (hipMalloc((void **)&df, bytes) != hipSuccess)
     return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-  hipError_t e = launch_get_state(L->q, L->storage, L->cp, L->buf[L->parity], df, L->stream);
+  hipError_t e = launch_get_state(L->q, L->storage, conv(L), L->buf[L->parity], df, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e == hipSuccess) e = hipMemcpy(f, df, bytes, hipMemcpyDeviceToHost);
   (void)hipFree(df);
@@ -896,7 +932,7 @@ int cmf_gather_sites(cmf_lattice *L, const int64_t *sites, int64_t n, double *ou
     return fail(CMF_ENOMEM, "hipMalloc failed");
   }
   hipError_t e = hipMemcpy(ds, sites, sizeof(int64_t) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_gather(L->q, L->storage, L->cp, L->buf[L->parity], ds, n, dout, L->stream);
+  if (e == hipSuccess) e = launch_gather(L->q, L->storage, conv(L), L->buf[L->parity], ds, n, dout, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(double) * L->q * n, hipMemcpyDeviceToHost);
   (void)hipFree(ds);
@@ -936,12 +972,8 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
   int rc = create_events(ev);
   if (rc != CMF_OK) return rc;
   for (int64_t s = 0; s < nsteps && rc == CMF_OK; ++s) {
-    const void *src = L->buf[L->parity];
-    void *dst = L->buf[1 - L->parity];
     hipError_t e = hipEventRecord(ev[2 * s], L->stream);
-    if (e == hipSuccess)
-      e = launch_step(L->q, L->storage, L->general, L->nt_stores, step_params(L), src, dst, L->step_dev,
-                      0, partials_buf(L, 0), L->grid, L->block, L->stream);
+    if (e == hipSuccess) e = launch_lattice_step(L, L->parity, 0, partials_buf(L, 0), L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
     if (e == hipSuccess)
       e = launch_finalize(partials_buf(L, 0), L->nparts, L->level2, L->series, L->cap, L->step_dev,
@@ -1033,7 +1065,7 @@ int cmf_sk_reset(cmf_lattice *L, int32_t nbins) {
 int cmf_sk_accumulate(cmf_lattice *L) {
   if (!L) return fail(CMF_EINVAL, "lattice is NULL");
   if (!L->sk_nbins) return fail(CMF_EINVAL, "call cmf_sk_reset first");
-  HIP_TRY(launch_macro_dev(L->q, L->storage, L->cp, L->buf[L->parity], L->sk_fields, L->stream));
+  HIP_TRY(launch_macro_dev(L->q, L->storage, conv(L), L->buf[L->parity], L->sk_fields, L->stream));
   for (int f = 0; f < 4; ++f) {
     hipfftResult fr = hipfftExecR2C(L->sk_plan, (hipfftReal *)(L->sk_fields + f * L->N),
                                     (hipfftComplex *)L->sk_F + f * L->sk_M);
@@ -1228,7 +1260,7 @@ int cmf_stats(cmf_lattice *L, cmf_moments *out, int64_t cap, int64_t *n_out) {
 
 int cmf_sample_macro(cmf_lattice *L, void *rho_dev, void *u_dev) {
   if (!L) return fail(CMF_EINVAL, "lattice is NULL");
-  HIP_TRY(launch_macro(L->q, L->storage, L->cp, L->buf[L->parity], (float *)rho_dev,
+  HIP_TRY(launch_macro(L->q, L->storage, conv(L), L->buf[L->parity], (float *)rho_dev,
                        (float *)u_dev, L->stream));
   return CMF_OK;
 }
@@ -1241,7 +1273,7 @@ int cmf_get_macro(cmf_lattice *L, double *rho, double *u) {
   const size_t bytes = sizeof(double) * 4 * L->N;
   if (hipMalloc((void **)&d, bytes) != hipSuccess)
     return fail(CMF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-  hipError_t e = launch_macro(L->q, L->storage, L->cp, L->buf[L->parity], d, d + L->N, L->stream);
+  hipError_t e = launch_macro(L->q, L->storage, conv(L), L->buf[L->parity], d, d + L->N, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e == hipSuccess && rho) e = hipMemcpy(rho, d, sizeof(double) * L->N, hipMemcpyDeviceToHost);
   if (e == hipSuccess && u) e = hipMemcpy(u, d + L->N, sizeof(double) * 3 * L->N, hipMemcpyDeviceToHost);
@@ -1274,13 +1306,13 @@ int cmf_velocity_pdf(cmf_lattice *L, int32_t nbins, double xmax, double *moments
   // pass 1: the means; pass 2: central moments about them; pass 3: histogram
   VelNorm c = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   double mean[3], var[3], m3[3], m4[3];
-  hipError_t e = launch_vel_moments(L->q, L->storage, L->cp, L->buf[L->parity], c, grid,
+  hipError_t e = launch_vel_moments(L->q, L->storage, conv(L), L->buf[L->parity], c, grid,
                                     partials, sums, L->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e == hipSuccess) {
     for (int a = 0; a < 3; ++a) c.centre[a] = mean[a] = h[4 * a] / n;
-    e = launch_vel_moments(L->q, L->storage, L->cp, L->buf[L->parity], c, grid, partials, sums,
+    e = launch_vel_moments(L->q, L->storage, conv(L), L->buf[L->parity], c, grid, partials, sums,
                            L->stream);
   }
   if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, L->stream);
@@ -1309,7 +1341,7 @@ int cmf_velocity_pdf(cmf_lattice *L, int32_t nbins, double xmax, double *moments
   if (e == hipSuccess && counts) {
     e = launch_zero_i64(reinterpret_cast<int64_t *>(dcounts), 3 * nb2, L->stream);
     if (e == hipSuccess)
-      e = launch_vel_hist(L->q, L->storage, L->cp, L->buf[L->parity], c, grid, nbins, xmax,
+      e = launch_vel_hist(L->q, L->storage, conv(L), L->buf[L->parity], c, grid, nbins, xmax,
                           dcounts, L->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(counts, dcounts, sizeof(unsigned long long) * 3 * nb2,
@@ -1440,6 +1472,8 @@ extern "C" int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst
                                 void *hip_stream) {
   int rc = validate(desc);
   if (rc != CMF_OK) return rc;
+  if (desc->flags & CMF_FLAG_IN_PLACE)
+    return fail(CMF_EUNSUPPORTED, "cmf_step_noalloc is a two-buffer pull step (no CMF_FLAG_IN_PLACE)");
   if (!src || !dst || src == dst) return fail(CMF_EINVAL, "src and dst must be two different buffers");
   if (reinterpret_cast<uintptr_t>(src) % 256 != 0 || reinterpret_cast<uintptr_t>(dst) % 256 != 0)
     return fail(CMF_EINVAL, "src and dst must be 256-byte aligned");
@@ -1472,7 +1506,8 @@ extern "C" int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = launch_set_i64(step_dev, step, s);
   if (e == hipSuccess)
-    e = launch_step(desc->q, desc->storage, mc.general, nt, f64 ? (const void *)&pd : (const void *)&pf,
+    e = launch_step(desc->q, desc->storage, mc.general, nt, kStreamPull,
+                    f64 ? (const void *)&pd : (const void *)&pf,
                     src, dst, step_dev, 0, scr, g, block, s);
   if (e == hipSuccess && stats_dev)
     e = launch_finalize(scr, g, scr + kScratchPartials, stats_dev, 1, step_dev, 0, 0, mass0, true, s);
@@ -1719,6 +1754,8 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     if (rc != CMF_OK) return fail(rc, "replica %d: %s", r, g_last_error.c_str());
     if (descs[r].storage != descs[0].storage) return fail(CMF_EINVAL, "replica %d: storage differs from replica 0", r);
     if (descs[r].flags != descs[0].flags) return fail(CMF_EINVAL, "replica %d: flags differ from replica 0", r);
+    if (descs[r].flags & CMF_FLAG_IN_PLACE)
+      return fail(CMF_EUNSUPPORTED, "replica %d: in-place streaming is for single lattices", r);
     // ensemble tiles address a replica's buffer (q arrays of N rounded up
     // to 64) with 32-bit byte offsets
     const int64_t n_pad = ((int64_t)descs[r].nx * descs[r].ny * descs[r].nz + 63) / 64 * 64;
@@ -1751,6 +1788,7 @@ int cmf_ensemble_create(const cmf_desc *descs, int32_t n, void *hip_stream, cmf_
     rp.cp.ny = descs[r].ny;
     rp.cp.nz = descs[r].nz;
     rp.cp.pitch = rp.pitch;
+    rp.cp.layout = kLayoutPull;
     rp.cp.rho0 = descs[r].rho0;
     for (int i = 0; i < descs[r].q; ++i) {
       rp.cp.w[i] = mcs[r].w[i];

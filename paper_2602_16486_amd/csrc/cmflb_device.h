@@ -131,6 +131,17 @@ __host__ __device__ constexpr int weight_class(int i) {
   return L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i];
 }
 
+// the population whose velocity is -c_i (every lattice here lists both
+// directions of each velocity)
+template <class L>
+__host__ __device__ constexpr int opposite(int i) {
+  for (int j = 0; j < L::Q; ++j)
+    if (L::cx[j] == -L::cx[i] && L::cy[j] == -L::cy[i] && L::cz[j] == -L::cz[i]) return j;
+  return -1;
+}
+static_assert(opposite<D2Q9>(5) == 7 && opposite<D3Q27>(0) == 0 && opposite<D3Q19>(1) == 2,
+              "opposite velocities");
+
 // tensor position (c_x + 1) + 3 (c_y + 1) [+ 9 (c_z + 1) in 3-D] of
 // population i
 template <class L>

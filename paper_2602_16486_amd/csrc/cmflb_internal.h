@@ -62,11 +62,27 @@ struct ReplicaParams {
   float scale[4], iscale[4];  // per weight class, as in StepParams
 };
 
+// Where the buffer keeps the pre-collision population f_i(x) of the next
+// step: kLayoutPull, slot i of site x - c_i (the post-collision value of
+// the step before, not yet streamed; two-buffer pull); with in-place (AA)
+// streaming, kLayoutNatural, slot i of site x (after an odd step), or
+// kLayoutSwapped, slot opposite(i) of site x - c_i (after an even step).
+enum Layout { kLayoutPull = 0, kLayoutNatural = 1, kLayoutSwapped = 2 };
+
+// Streaming form of a step launch: the two-buffer pull, or the two halves
+// of in-place streaming.  AA even step: read slot i of own site, write the
+// post-collision population i to slot opposite(i) of own site; AA odd
+// step: read slot opposite(i) of site x - c_i, write slot i of site
+// x + c_i.  Every buffer element is read and written by one site only.
+enum StreamMode { kStreamPull = 0, kStreamAAEven = 1, kStreamAAOdd = 2 };
+
 // Parameters of the state conversion kernels (FP64 always).  pitch = 0:
 // the row-interleaved layout of a single lattice; pitch > 0: one array per
 // population, population i starting at element i pitch (ensemble replicas).
+// layout: a Layout value.
 struct ConvParams {
   int32_t nx, ny, nz;
+  int32_t layout;
   int64_t pitch;
   double rho0;
   double w[27];
@@ -81,7 +97,8 @@ enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 // captured in a graph pass offsets 0, 1, ... and advance *step_ptr once at
 // their end (launch_bump_step); a direct step passes 0 and its finalize
 // advances *step_ptr by bump = 1.
-hipError_t launch_step(int q, int storage, bool general, bool nt,
+// mode: a StreamMode value; src == dst for the in-place modes.
+hipError_t launch_step(int q, int storage, bool general, bool nt, int mode,
                        const void *params, const void *src, void *dst,
                        const int64_t *step_ptr, int step_off, double *partials,
                        int grid, int block, hipStream_t stream);

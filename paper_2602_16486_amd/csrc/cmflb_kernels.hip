@@ -606,6 +606,123 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(
   block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride, acc_lds);
 }
 
+// In-place (AA) streaming, buffer-addressed like load_site_buf (every z
+// plane below 4 GiB).  Even step (ODD = false): the populations of the
+// site's own slots in, post-collision population i out to slot
+// opposite(i) of the same site.  Odd step: slot opposite(i) of site
+// x - c_i in (where the even step left f*_i), slot i of site x + c_i out.
+// NT (population rows of whole cache lines): non-temporal accesses where a
+// tile covers whole rows, every access of the even step and the c_x = 0
+// accesses of the odd step.
+template <class L, typename S, typename R, bool NT, bool ODD>
+__device__ __forceinline__ void load_site_aa(R *d, const S *buf, const float *scale, int nx,
+                                             int ny, int nz, int x, int y, int z) {
+  using ST = Store<S, R>;
+  constexpr uint32_t B = sizeof(S);
+  const int64_t plane = (int64_t)ny * L::Q * nx;
+  const uint32_t pbytes = (uint32_t)(plane * B);
+  const uint32_t rowb = (uint32_t)nx * B;
+  if constexpr (!ODD) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + (int64_t)z * plane, pbytes);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+      d[i] = ST::from_bits(buf_load<S, NT>(r, (uint32_t)x * B, ((uint32_t)y * L::Q + i) * rowb),
+                           scale[weight_class<L>(i)]);
+  } else {
+    __amdgpu_buffer_rsrc_t rs[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int zs = L::D == 3 ? wrap_sub(z, b - 1, nz) : z;
+      rs[b] = make_rsrc(buf + (int64_t)zs * plane, pbytes);
+    }
+    const uint32_t xs[3] = {(uint32_t)(x == nx - 1 ? 0 : x + 1) * B, (uint32_t)x * B,
+                            (uint32_t)(x == 0 ? nx - 1 : x - 1) * B};
+    uint32_t ys[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ys[a] = (uint32_t)wrap_sub(y, a - 1, ny);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const uint32_t soff = (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)opposite<L>(i)) * rowb;
+      const float sc = scale[weight_class<L>(i)];
+      if (NT && L::cx[i] == 0)
+        d[i] = ST::from_bits(buf_load<S, true>(rs[L::cz[i] + 1], xs[1], soff), sc);
+      else
+        d[i] = ST::from_bits(buf_load<S, false>(rs[L::cz[i] + 1], xs[L::cx[i] + 1], soff), sc);
+    }
+  }
+}
+
+template <class L, typename S, typename R, bool NT, bool ODD>
+__device__ __forceinline__ void store_site_aa(const R *d, S *buf, const float *iscale, int nx,
+                                              int ny, int nz, int x, int y, int z) {
+  using ST = Store<S, R>;
+  constexpr uint32_t B = sizeof(S);
+  const int64_t plane = (int64_t)ny * L::Q * nx;
+  const uint32_t pbytes = (uint32_t)(plane * B);
+  const uint32_t rowb = (uint32_t)nx * B;
+  if constexpr (!ODD) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + (int64_t)z * plane, pbytes);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+      buf_store<S, NT>(ST::to_bits(d[i], iscale[weight_class<L>(i)]), r, (uint32_t)x * B,
+                       ((uint32_t)y * L::Q + (uint32_t)opposite<L>(i)) * rowb);
+  } else {
+    // destination plane z + c_z, row y + c_y, column x + c_x (index c + 1)
+    __amdgpu_buffer_rsrc_t rd[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int zd = L::D == 3 ? wrap_sub(z, 1 - b, nz) : z;
+      rd[b] = make_rsrc(buf + (int64_t)zd * plane, pbytes);
+    }
+    const uint32_t xd[3] = {(uint32_t)(x == 0 ? nx - 1 : x - 1) * B, (uint32_t)x * B,
+                            (uint32_t)(x == nx - 1 ? 0 : x + 1) * B};
+    uint32_t yd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) yd[a] = (uint32_t)wrap_sub(y, 1 - a, ny);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const uint32_t soff = (yd[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)i) * rowb;
+      const R v = d[i];
+      if (NT && L::cx[i] == 0)
+        buf_store<S, true>(ST::to_bits(v, iscale[weight_class<L>(i)]), rd[L::cz[i] + 1], xd[1], soff);
+      else
+        buf_store<S, false>(ST::to_bits(v, iscale[weight_class<L>(i)]), rd[L::cz[i] + 1],
+                            xd[L::cx[i] + 1], soff);
+    }
+  }
+}
+
+// The fused step with in-place streaming on one buffer (the even or the odd
+// half of a pair of steps); tiles, statistics and ONE as in k_step.  Every
+// element is read and then written by the same thread only, and each store
+// depends on every load of its site through the collision.
+template <class L, typename S, typename R, bool GENERAL, bool NT, bool ONE, bool ODD>
+__global__ __launch_bounds__(kMaxBlock) void k_step_aa(
+    S *buf, const StepParams<R> p, const int64_t *__restrict__ step_ptr, int step_off,
+    double *__restrict__ partials) {
+  constexpr int Q = L::Q;
+  const uint64_t step = (uint64_t)(*step_ptr + step_off);
+  const int BX = blockDim.x;
+  const int nx = p.nx, ny = p.ny;
+  using A = typename std::conditional<ONE, SiteStats<R>, Acc>::type;
+  A acc{};
+
+  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+    const TileXY c = tile_coords(tile, p.nxb, ny, BX);
+    if (c.x < nx) {
+      R d[Q];
+      load_site_aa<L, S, R, NT, ODD>(d, buf, p.scale, nx, ny, p.nz, c.x, c.y, c.z);
+      const int64_t row = (int64_t)c.y + (int64_t)ny * c.z;
+      const int site = (int)(c.x + nx * row);
+      collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, (uint32_t)site, step, acc);
+      store_site_aa<L, S, R, NT, ODD>(d, buf, p.iscale, nx, ny, p.nz, c.x, c.y, c.z);
+    }
+    if constexpr (ONE) break;
+  }
+  extern __shared__ double acc_lds[];
+  block_store_acc(acc, partials + (int64_t)blockIdx.x * kPartStride, acc_lds);
+}
+
 // ---------------------------------------------------------------------------
 // statistics finalize: fixed-order FP64 sums of the block partials (in two
 // levels when there are many blocks) into the series row of the current
@@ -691,6 +808,15 @@ __device__ __forceinline__ int64_t shifted_site(const ConvParams &cp, int64_t s,
   return xs + (int64_t)cp.nx * (ys + (int64_t)cp.ny * zs);
 }
 
+// element offset of the pre-collision population f_i of site s in the
+// buffer, for the buffer's layout (cp.layout)
+template <class L>
+__device__ __forceinline__ int64_t state_offset(const ConvParams &cp, int i, int64_t s) {
+  if (cp.layout == kLayoutNatural) return pop_site_offset<L::Q>(cp, i, s);
+  const int slot = cp.layout == kLayoutSwapped ? opposite<L>(i) : i;
+  return pop_site_offset<L::Q>(cp, slot, shifted_site<L>(cp, s, i, -1));
+}
+
 // d_eq = f_eq(rho, u) - w rho0 = T(u)^-1 (rho e_0 - rho0 G(u)), evaluated at
 // site s and written to the buffer slot that the next pull reads from.
 template <class L, typename S>
@@ -716,7 +842,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const ConvParams cp,
     d3q19::populations(t, dd);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-      ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)), dd[i],
+      ST::store(buf + state_offset<L>(cp, i, s), dd[i],
                 cp.iscale[i]);
   } else {
     add_rest_moments<L::D, double>(t, -cp.rho0, ux, uy, uz);
@@ -724,7 +850,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const ConvParams cp,
     tensor_inv<L::D, double>(t, ax, ay, az);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-      ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+      ST::store(buf + state_offset<L>(cp, i, s),
                 t[pop_pos<L>(i)], cp.iscale[i]);
   }
 }
@@ -739,7 +865,7 @@ __global__ __launch_bounds__(256) void k_set_state(const ConvParams cp,
   if (s >= N) return;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    ST::store(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+    ST::store(buf + state_offset<L>(cp, i, s),
               f[(int64_t)i * N + s] - cp.w[i] * cp.rho0, cp.iscale[i]);
 }
 
@@ -755,7 +881,7 @@ __global__ __launch_bounds__(256) void k_get_state(const ConvParams cp,
   for (int i = 0; i < L::Q; ++i)
     f[(int64_t)i * N + s] =
         cp.w[i] * cp.rho0 +
-        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+        ST::load(buf + state_offset<L>(cp, i, s),
                  cp.scale[i]);
 }
 
@@ -773,7 +899,7 @@ __global__ __launch_bounds__(256) void k_gather(const ConvParams cp,
   for (int i = 0; i < L::Q; ++i)
     out[k * L::Q + i] =
         cp.w[i] * cp.rho0 +
-        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+        ST::load(buf + state_offset<L>(cp, i, s),
                  cp.scale[i]);
 }
 
@@ -790,7 +916,7 @@ __global__ __launch_bounds__(256) void k_macro(const ConvParams cp,
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const double d =
-        ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+        ST::load(buf + state_offset<L>(cp, i, s),
                  cp.scale[i]);
     drho += d;
     j[0] += L::cx[i] * d;
@@ -869,7 +995,7 @@ __global__ __launch_bounds__(256) void k_macro_dev(const ConvParams cp,
   double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const double d = ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+    const double d = ST::load(buf + state_offset<L>(cp, i, s),
                               cp.scale[i]);
     drho += d;
     j[0] += L::cx[i] * d;
@@ -973,7 +1099,7 @@ __device__ __forceinline__ void site_velocity(const ConvParams &cp,
   double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const double d = ST::load(buf + pop_site_offset<L::Q>(cp, i, shifted_site<L>(cp, s, i, -1)),
+    const double d = ST::load(buf + state_offset<L>(cp, i, s),
                               cp.scale[i]);
     drho += d;
     j[0] += L::cx[i] * d;
@@ -1237,69 +1363,82 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <class L, typename S, typename R, bool G, bool NT, bool BUF>
+// MODE: a StreamMode (the in-place modes only with BUF)
+template <class L, typename S, typename R, bool G, bool NT, bool BUF, int MODE>
 hipError_t step_shape(const StepParams<R> &p, const void *src, void *dst,
                       const int64_t *step_ptr, int step_off, double *partials, int grid,
                       int block, hipStream_t stream) {
+  auto go = [&](auto one, int nblocks, size_t lds) {
+    constexpr bool ONE = decltype(one)::value;
+    if constexpr (MODE == kStreamPull)
+      hipLaunchKernelGGL((k_step<L, S, R, G, NT, ONE, BUF>), dim3(nblocks), dim3(block), lds,
+                         stream, static_cast<const S *>(src), static_cast<S *>(dst), p, step_ptr,
+                         step_off, partials);
+    else
+      hipLaunchKernelGGL((k_step_aa<L, S, R, G, NT, ONE, MODE == kStreamAAOdd>), dim3(nblocks),
+                         dim3(block), lds, stream, static_cast<S *>(dst), p, step_ptr, step_off,
+                         partials);
+    return hipGetLastError();
+  };
   // one workgroup per tile: per-site statistics (measured faster for D2Q9,
   // 4096^2 FP32 0.218 -> 0.205 ms; 1-2% slower for the 3-D lattices, whose
   // kernels then keep the FP64 accumulation)
-  if constexpr (L::Q == 9) {
-    if (grid >= p.ntiles) {
-      hipLaunchKernelGGL((k_step<L, S, R, G, NT, true, BUF>), dim3(p.ntiles), dim3(block),
-                         acc_lds_bytes<R>(block), stream, static_cast<const S *>(src),
-                         static_cast<S *>(dst), p, step_ptr, step_off, partials);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((k_step<L, S, R, G, NT, false, BUF>), dim3(grid), dim3(block),
-                     acc_lds_bytes<double>(block), stream, static_cast<const S *>(src),
-                     static_cast<S *>(dst), p, step_ptr, step_off, partials);
-  return hipGetLastError();
+  if constexpr (L::Q == 9)
+    if (grid >= p.ntiles) return go(std::true_type{}, p.ntiles, acc_lds_bytes<R>(block));
+  return go(std::false_type{}, grid, acc_lds_bytes<double>(block));
 }
 
 template <class L, typename S, typename R, bool G, bool NT>
-hipError_t step_one(const void *params, const void *src, void *dst,
+hipError_t step_one(int mode, const void *params, const void *src, void *dst,
                     const int64_t *step_ptr, int step_off, double *partials, int grid,
                     int block, hipStream_t stream) {
   const StepParams<R> &p = *static_cast<const StepParams<R> *>(params);
   // buffer-addressed accesses when every z plane (ny Q nx values) of a
-  // population buffer spans less than 4 GiB
+  // population buffer spans less than 4 GiB (always so for in-place
+  // streaming, which the library accepts only then)
   const bool buf = (int64_t)p.ny * L::Q * p.nx * (int64_t)sizeof(S) < ((int64_t)1 << 32);
+  if (mode != kStreamPull) {
+    if (!buf || src != dst) return hipErrorInvalidValue;
+    return mode == kStreamAAEven
+               ? step_shape<L, S, R, G, NT, true, kStreamAAEven>(p, src, dst, step_ptr, step_off,
+                                                                 partials, grid, block, stream)
+               : step_shape<L, S, R, G, NT, true, kStreamAAOdd>(p, src, dst, step_ptr, step_off,
+                                                                partials, grid, block, stream);
+  }
   if (buf)
-    return step_shape<L, S, R, G, NT, true>(p, src, dst, step_ptr, step_off, partials, grid,
-                                            block, stream);
-  return step_shape<L, S, R, G, NT, false>(p, src, dst, step_ptr, step_off, partials, grid,
-                                           block, stream);
+    return step_shape<L, S, R, G, NT, true, kStreamPull>(p, src, dst, step_ptr, step_off,
+                                                         partials, grid, block, stream);
+  return step_shape<L, S, R, G, NT, false, kStreamPull>(p, src, dst, step_ptr, step_off,
+                                                        partials, grid, block, stream);
 }
 
 template <class L, typename S, typename R>
-hipError_t step_lg(bool general, bool nt, const void *params, const void *src,
+hipError_t step_lg(bool general, bool nt, int mode, const void *params, const void *src,
                    void *dst, const int64_t *step_ptr, int off, double *partials,
                    int grid, int block, hipStream_t stream) {
   if (general)
-    return nt ? step_one<L, S, R, true, true>(params, src, dst, step_ptr, off, partials, grid, block, stream)
-              : step_one<L, S, R, true, false>(params, src, dst, step_ptr, off, partials, grid, block, stream);
-  return nt ? step_one<L, S, R, false, true>(params, src, dst, step_ptr, off, partials, grid, block, stream)
-            : step_one<L, S, R, false, false>(params, src, dst, step_ptr, off, partials, grid, block, stream);
+    return nt ? step_one<L, S, R, true, true>(mode, params, src, dst, step_ptr, off, partials, grid, block, stream)
+              : step_one<L, S, R, true, false>(mode, params, src, dst, step_ptr, off, partials, grid, block, stream);
+  return nt ? step_one<L, S, R, false, true>(mode, params, src, dst, step_ptr, off, partials, grid, block, stream)
+            : step_one<L, S, R, false, false>(mode, params, src, dst, step_ptr, off, partials, grid, block, stream);
 }
 
 template <class L>
-hipError_t step_l(int storage, bool general, bool nt, const void *params,
+hipError_t step_l(int storage, bool general, bool nt, int mode, const void *params,
                   const void *src, void *dst, const int64_t *step_ptr, int off,
                   double *partials, int grid, int block, hipStream_t stream) {
   switch (storage) {
     case kF64:
-      return step_lg<L, double, double>(general, nt, params, src, dst, step_ptr, off,
+      return step_lg<L, double, double>(general, nt, mode, params, src, dst, step_ptr, off,
                                         partials, grid, block, stream);
     case kF32:
-      return step_lg<L, float, float>(general, nt, params, src, dst, step_ptr, off,
+      return step_lg<L, float, float>(general, nt, mode, params, src, dst, step_ptr, off,
                                       partials, grid, block, stream);
     case kF16:
-      return step_lg<L, __half, float>(general, nt, params, src, dst, step_ptr, off,
+      return step_lg<L, __half, float>(general, nt, mode, params, src, dst, step_ptr, off,
                                        partials, grid, block, stream);
     case kBF16:
-      return step_lg<L, __hip_bfloat16, float>(general, nt, params, src, dst,
+      return step_lg<L, __hip_bfloat16, float>(general, nt, mode, params, src, dst,
                                                step_ptr, off, partials, grid, block,
                                                stream);
   }
@@ -1308,18 +1447,20 @@ hipError_t step_l(int storage, bool general, bool nt, const void *params,
 
 }  // namespace
 
-hipError_t launch_step(int q, int storage, bool general, bool nt,
+hipError_t launch_step(int q, int storage, bool general, bool nt, int mode,
                        const void *params, const void *src, void *dst,
                        const int64_t *step_ptr, int step_off, double *partials,
                        int grid, int block, hipStream_t stream) {
+  if (mode != kStreamPull && mode != kStreamAAEven && mode != kStreamAAOdd)
+    return hipErrorInvalidValue;
   if (q == 9)
-    return step_l<D2Q9>(storage, general, nt, params, src, dst, step_ptr, step_off,
+    return step_l<D2Q9>(storage, general, nt, mode, params, src, dst, step_ptr, step_off,
                         partials, grid, block, stream);
   if (q == 19)
-    return step_l<D3Q19>(storage, general, nt, params, src, dst, step_ptr, step_off,
+    return step_l<D3Q19>(storage, general, nt, mode, params, src, dst, step_ptr, step_off,
                          partials, grid, block, stream);
   if (q == 27)
-    return step_l<D3Q27>(storage, general, nt, params, src, dst, step_ptr, step_off,
+    return step_l<D3Q27>(storage, general, nt, mode, params, src, dst, step_ptr, step_off,
                          partials, grid, block, stream);
   return hipErrorInvalidValue;
 }

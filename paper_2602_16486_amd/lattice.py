@@ -39,11 +39,12 @@ def rate_vector(q, tau, kind="paper"):
     return lam
 
 
-def external_bytes(q, shape, storage="f32"):
-    """Device bytes a lattice needs for its two population buffers when they
-    are provided by the caller (``Lattice(..., external=(ptr, nbytes))``)."""
+def external_bytes(q, shape, storage="f32", in_place=False):
+    """Device bytes a lattice needs for its population buffers (two, or one
+    with ``in_place``) when they are provided by the caller
+    (``Lattice(..., external=(ptr, nbytes))``)."""
     lib = _lib.load()
-    d, _ = _lib.make_desc(q, shape, storage=storage)
+    d, _ = _lib.make_desc(q, shape, storage=storage, flags=_lib.FLAG_IN_PLACE if in_place else 0)
     n = lib.cmf_external_bytes(ctypes.byref(d))
     if n == 0:
         raise ValueError("invalid lattice description")
@@ -58,11 +59,14 @@ class Lattice:
     ``stream`` an optional hipStream_t handle (int), e.g.
     ``torch.cuda.current_stream().cuda_stream``; ``external`` an optional
     (device pointer, bytes) pair of caller-owned memory for the population
-    buffers (see :func:`external_bytes`), e.g. from a torch tensor.
+    buffers (see :func:`external_bytes`), e.g. from a torch tensor;
+    ``in_place`` in-place (AA) streaming on one population buffer (half the
+    population memory, the same results bit for bit).
     """
 
     def __init__(self, q, shape, storage="f32", rho0=1.0, tau=0.8, kT=0.0, lam=None, seed=1,
-                 replica=0, flags=0, stream=None, series_capacity=0, external=None):
+                 replica=0, flags=0, stream=None, series_capacity=0, external=None,
+                 in_place=False):
         self._lib = _lib.load()
         nx, ny, nz = (tuple(int(s) for s in shape) + (1, 1))[:3]
         self.q = int(q)
@@ -72,7 +76,7 @@ class Lattice:
         d = _lib.Desc()
         d.q, d.nx, d.ny, d.nz = self.q, nx, ny, nz
         d.storage = _lib.STORAGE[storage]
-        d.flags = flags
+        d.flags = flags | (_lib.FLAG_IN_PLACE if in_place else 0)
         d.rho0, d.tau, d.kT = float(rho0), float(tau), float(kT)
         self._lam = None
         if lam is not None:

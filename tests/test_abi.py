@@ -184,3 +184,25 @@ def test_ensemble_create_rejects_before_any_device_call():
         assert rc == _lib.CMF_EINVAL, msg
         assert msg in lib.cmf_last_error().decode()
         assert not h.value
+
+
+def test_in_place_checks_before_any_device_call():
+    """CMF_FLAG_IN_PLACE: cmf_external_bytes counts one population buffer;
+    a z plane of 4 GiB or more (in-place steps address a plane with 32-bit
+    byte offsets), an ensemble member and cmf_step_noalloc (a two-buffer
+    step) are refused with CMF_EUNSUPPORTED before any device call."""
+    lib = _lib.load()
+    d, _ = _lib.make_desc(27, (10, 6, 4), storage="f32", flags=_lib.FLAG_IN_PLACE)
+    assert lib.cmf_external_bytes(ctypes.byref(d)) == (27 * 240 * 4 + 255) // 256 * 256
+    big, _ = _lib.make_desc(27, (8192, 8192, 1), storage="f64", flags=_lib.FLAG_IN_PLACE)
+    assert lib.cmf_external_bytes(ctypes.byref(big)) == 0
+    h = ctypes.c_void_p()
+    assert lib.cmf_create(ctypes.byref(big), None, ctypes.byref(h)) == _lib.CMF_EUNSUPPORTED
+    assert b"4 GiB" in lib.cmf_last_error() and not h.value
+    descs = (_lib.Desc * 1)()
+    descs[0] = d
+    assert lib.cmf_ensemble_create(descs, 1, None, ctypes.byref(h)) == _lib.CMF_EUNSUPPORTED
+    assert b"single lattices" in lib.cmf_last_error() and not h.value
+    rc = lib.cmf_step_noalloc(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_void_p(8192), 0, 256, 1,
+                              None, None)
+    assert rc == _lib.CMF_EUNSUPPORTED and b"IN_PLACE" in lib.cmf_last_error()
