@@ -35,9 +35,11 @@ ALG_BYTES = 2 * 27 * 4 * N
 COPY_BYTES = 27 * N * 4  # per direction
 
 CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d out/prof_trace -o trace --output-format csv "
-             "-- python3 bench.py --steps 400 --warmup 64 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
+             "-- python3 bench.py --steps 400 --warmup 64 --variants \"\" --d3q19 \"\" --in-place \"\" --no-cpu "
+             "--no-tune --no-ensemble")
 CMD_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d out/prof_fetch -o fetch --output-format csv "
-             "-- python3 bench.py --steps 10 --warmup 32 --variants \"\" --d3q19 \"\" --no-cpu --no-tune --no-ensemble")
+             "-- python3 bench.py --steps 10 --warmup 32 --variants \"\" --d3q19 \"\" --in-place \"\" --no-cpu "
+             "--no-tune --no-ensemble")
 CMD_WRITE = CMD_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("prof_fetch", "prof_write").replace(
     "-o fetch", "-o write")
 
@@ -130,9 +132,14 @@ def main(outdir):
     print("\n".join(lines))
 
 
-ENS_KERNEL = "void cmf::k_ensemble_step<float, float, false, false>"
+ENS_KERNEL = "void cmf::k_ensemble_step<float, float, false>"
 CMD_ENS = ("rocprofv3 --kernel-trace --stats -d out/prof_ens -o ens --output-format csv "
-           "-- python3 bench.py --steps 50 --warmup 16 --variants \"\" --d3q19 \"\" --no-cpu --no-tune")
+           "-- python3 bench.py --steps 50 --warmup 16 --variants \"\" --d3q19 \"\" --in-place \"\" --no-cpu "
+           "--no-tune")
+CMD_ENS_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d out/prof_ens_fetch -o ens_fetch --output-format csv "
+                 "-- python3 bench.py --steps 10 --warmup 8 --variants \"\" --d3q19 \"\" --in-place \"\" "
+                 "--no-cpu --no-tune")
+CMD_ENS_WRITE = CMD_ENS_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("ens_fetch", "ens_write")
 
 
 def ensemble_summary(outdir):
@@ -177,8 +184,32 @@ def ensemble_summary(outdir):
         f"{len(durs)} dispatches (bench.py's HIP-event figure: {e['kernel_ms']:.4f} ms); "
         f"{alg / (med * 1e-9) / 1e9:.0f} GB/s algorithmic = {alg / (med * 1e-9) / 8e12:.3f} of 8 TB/s, "
         f"{e['sites'] / (med * 1e-9) / 1e9:.1f} GLUPS.",
+        f"Time split (one launch over the D2Q9 replicas only, one over the D3Q27 replicas only, same tiles): "
+        f"{e['split_kernel_ms']['d2q9_ms']:.4f} / {e['split_kernel_ms']['d3q27_ms']:.4f} ms; idle lanes "
+        f"{e['idle_lane_fraction']['d2q9'] * 100:.2f} % / {e['idle_lane_fraction']['d3q27'] * 100:.2f} %.",
         "",
     ]
+    fpath = os.path.join(outdir, "prof_ens_fetch", "ens_fetch_counter_collection.csv")
+    wpath = os.path.join(outdir, "prof_ens_write", "ens_write_counter_collection.csv")
+    if os.path.exists(fpath) and os.path.exists(wpath):
+        fe, nf = _median_counter(fpath, ENS_KERNEL)
+        fc, _ = _median_counter(fpath, COPY_KERNEL)
+        we, nw = _median_counter(wpath, ENS_KERNEL)
+        wc, _ = _median_counter(wpath, COPY_KERNEL)
+        rb, wb = fe * 1024 * COPY_BYTES / (fc * 1024), we * 1024 * COPY_BYTES / (wc * 1024)
+        lines += [
+            "HBM bytes (same environment, calibrated by the plain copy kernel of the same runs as for the step "
+            "kernel):",
+            "",
+            "    " + CMD_ENS_FETCH,
+            "    " + CMD_ENS_WRITE,
+            "",
+            f"Ensemble kernel ({nf}/{nw} dispatches, medians): FETCH_SIZE {fe:.0f} KiB, WRITE_SIZE {we:.0f} KiB; "
+            f"read {rb / 1e9:.3f} GB + write {wb / 1e9:.3f} GB = {(rb + wb) / 1e9:.3f} GB per launch, "
+            f"{(rb + wb) / alg:.3f} x the algorithmic {alg / 1e9:.3f} GB (reads {rb / (alg / 2):.3f} x, "
+            f"writes {wb / (alg / 2):.3f} x).",
+            "",
+        ]
     with open(os.path.join(ROOT, "profiles", "k_ensemble_step_mixed320.md"), "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
@@ -193,7 +224,17 @@ VARIANTS = [  # (kernel name prefix, label, q, bytes per stored value, bench.py 
      ("variants", "bf16")),
     ("void cmf::k_step<cmf::D3Q19, float, float, false, true, false, true>", "D3Q19 FP32", 19, 4, ("lattices", "d3q19_f32")),
     ("void cmf::k_step<cmf::D3Q19, __half, float, false, true, false, true>", "D3Q19 FP16", 19, 2, ("lattices", "d3q19_f16")),
+    ("void cmf::k_step_aa<cmf::D3Q27, float, float, false, true, false, false>", "D3Q27 FP32 in place, even step", 27, 4,
+     ("in_place", "f32")),
+    ("void cmf::k_step_aa<cmf::D3Q27, float, float, false, true, false, true>", "D3Q27 FP32 in place, odd step", 27, 4,
+     ("in_place", "f32")),
 ]
+
+
+CMD_IP_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d out/prof_ip_fetch -o ip_fetch --output-format csv "
+                "-- python3 bench.py --steps 10 --warmup 8 --variants \"\" --d3q19 \"\" --no-cpu --no-tune "
+                "--no-ensemble")
+CMD_IP_WRITE = CMD_IP_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("ip_fetch", "ip_write")
 
 
 def variants_summary(outdir):
@@ -239,8 +280,24 @@ def variants_summary(outdir):
         avg = sum(durs) / len(durs)
         lines.append(f"| {label} `{prefix[10:]}` | {len(durs)} | {avg / 1e6:.4f} | {med / 1e6:.4f} | {live:.4f} | "
                      f"{2 * q * sbytes} | {alg / (med * 1e-9) / 1e9:.0f} | {alg / (med * 1e-9) / 8e12:.3f} |")
+    fpath = os.path.join(outdir, "prof_ip_fetch", "ip_fetch_counter_collection.csv")
+    wpath = os.path.join(outdir, "prof_ip_write", "ip_write_counter_collection.csv")
+    if os.path.exists(fpath) and os.path.exists(wpath):
+        fc, _ = _median_counter(fpath, COPY_KERNEL)
+        wc, _ = _median_counter(wpath, COPY_KERNEL)
+        lines += ["", "HBM bytes of the FP32 pull and in-place kernels (FETCH_SIZE, then WRITE_SIZE, calibrated by the "
+                  "plain copy kernel of the same runs):", "", "    " + CMD_IP_FETCH, "    " + CMD_IP_WRITE, "",
+                  "| kernel | dispatches | read GB | write GB | traffic / algorithmic |", "|---|---|---|---|---|"]
+        alg = 2 * 27 * 4 * N
+        for prefix, label in ((STEP_KERNEL, "D3Q27 FP32 pull"), (VARIANTS[-2][0], VARIANTS[-2][1]),
+                              (VARIANTS[-1][0], VARIANTS[-1][1])):
+            fk, nf = _median_counter(fpath, prefix)
+            wk, _ = _median_counter(wpath, prefix)
+            rb, wb = fk * COPY_BYTES / fc, wk * COPY_BYTES / wc
+            lines.append(f"| {label} | {nf} | {rb / 1e9:.3f} | {wb / 1e9:.3f} | {(rb + wb) / alg:.3f} |")
     lines += ["", "The 16-bit kernels are bound by instruction issue (the Philox4x32-10 and Box-Muller noise is "
-              "about two thirds of it), not by HBM.", ""]
+              "about two thirds of it), not by HBM.  The in-place (AA) pair streams the same bytes in one buffer; "
+              "bench.py's live figure for it is the average over even and odd steps.", ""]
     with open(os.path.join(ROOT, "profiles", "k_step_variants_256cube.md"), "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
@@ -249,7 +306,7 @@ def variants_summary(outdir):
 VALU_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_SALU "
                  "SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE")
 CMD_VALU = ("CMFLB_TUNE_CACHE=out/tune.txt rocprofv3 --pmc " + VALU_COUNTERS + " -d out/prof_valu -o valu --output-format csv "
-            "-- python3 bench.py --steps 10 --warmup 8 --no-cpu --no-tune --no-ensemble")
+            "-- python3 bench.py --steps 10 --warmup 8 --in-place \"\" --no-cpu --no-tune --no-ensemble")
 CU_NUM = 256
 XCC_NUM = 8
 
