@@ -1246,26 +1246,32 @@ __device__ __forceinline__ void ensemble_site(__amdgpu_buffer_rsrc_t rs, __amdgp
   const uint32_t nx = (uint32_t)p.nx, ny = (uint32_t)p.ny;
   const uint32_t us = (uint32_t)s;
   const uint32_t row = udiv_invariant(us, p.div_nx, p.sh_nx);
-  const int x = (int)(us - row * nx);
-  const uint32_t zr = udiv_invariant(row, p.div_ny, p.sh_ny);
-  const int y = (int)(row - zr * ny);
-  const int z = (int)zr;
-  const uint32_t xs[3] = {(uint32_t)(x == p.nx - 1 ? 0 : x + 1), (uint32_t)x,
-                          (uint32_t)(x == 0 ? p.nx - 1 : x - 1)};
-  uint32_t srow[3][3];  // first site of each source row
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const uint32_t ys = (uint32_t)wrap_sub(y, a - 1, p.ny);
-      const uint32_t zs = L::D == 3 ? (uint32_t)wrap_sub(z, b - 1, p.nz) : (uint32_t)z;
-      srow[a][b] = (ys + ny * zs) * nx;
-    }
+  const uint32_t x = us - row * nx;
+  uint32_t y = row, z = 0;
+  if constexpr (L::D == 3) {
+    z = udiv_invariant(row, p.div_ny, p.sh_ny);
+    y = row - z * ny;
+  }
+  // byte offsets from site s to the source site x - c along each axis
+  // (index c + 1), periodic; unsigned arithmetic wraps, the sums land in
+  // [0, N) sites
+  const uint32_t plane = nx * ny;
+  const uint32_t dx[3] = {(x == nx - 1 ? 0u - (nx - 1) : 1u) * B, 0u,
+                          (x == 0 ? nx - 1 : 0u - 1u) * B};
+  const uint32_t dy[3] = {(y == ny - 1 ? 0u - (ny - 1) * nx : nx) * B, 0u,
+                          (y == 0 ? (ny - 1) * nx : 0u - nx) * B};
+  uint32_t dz[3] = {0u, 0u, 0u};
+  if constexpr (L::D == 3) {
+    const uint32_t nz = (uint32_t)p.nz;
+    dz[0] = (z == nz - 1 ? 0u - (nz - 1) * plane : plane) * B;
+    dz[2] = (z == 0 ? (nz - 1) * plane : 0u - plane) * B;
+  }
+  const uint32_t sb = us * B;
   const uint32_t popb = (uint32_t)p.pitch * B;
   R d[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const uint32_t voff = (srow[L::cy[i] + 1][L::cz[i] + 1] + xs[L::cx[i] + 1]) * B;
+    const uint32_t voff = sb + dx[L::cx[i] + 1] + dy[L::cy[i] + 1] + dz[L::cz[i] + 1];
     const float sc = p.scale[weight_class<L>(i)];
     if (L::cx[i] == 0 && L::cy[i] == 0 && L::cz[i] == 0)
       d[i] = ST::from_bits(buf_load<S, true>(rs, voff, (uint32_t)i * popb), sc);
@@ -1273,10 +1279,9 @@ __device__ __forceinline__ void ensemble_site(__amdgpu_buffer_rsrc_t rs, __amdgp
       d[i] = ST::from_bits(buf_load<S, false>(rs, voff, (uint32_t)i * popb), sc);
   }
   collide_site<L, R, GENERAL, sizeof(S) == 2>(d, p, us, step, acc);
-  const uint32_t voff = us * B;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    buf_store<S, true>(ST::to_bits(d[i], p.iscale[weight_class<L>(i)]), rd, voff, (uint32_t)i * popb);
+    buf_store<S, true>(ST::to_bits(d[i], p.iscale[weight_class<L>(i)]), rd, sb, (uint32_t)i * popb);
 }
 
 // Workgroups are handed to the XCDs round-robin by id and every XCD has its
