@@ -140,6 +140,9 @@ CMD_ENS_FETCH = ("rocprofv3 --pmc FETCH_SIZE -d out/prof_ens_fetch -o ens_fetch 
                  "-- python3 bench.py --steps 10 --warmup 8 --variants \"\" --d3q19 \"\" --in-place \"\" "
                  "--no-cpu --no-tune")
 CMD_ENS_WRITE = CMD_ENS_FETCH.replace("FETCH_SIZE", "WRITE_SIZE").replace("ens_fetch", "ens_write")
+CMD_ENS_VALU = CMD_ENS_FETCH.replace("FETCH_SIZE", "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES "
+                                     "SQ_WAVE_CYCLES SQ_INSTS_SALU SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE").replace(
+    "ens_fetch", "ens_valu")
 
 
 def ensemble_summary(outdir):
@@ -208,6 +211,26 @@ def ensemble_summary(outdir):
             f"read {rb / 1e9:.3f} GB + write {wb / 1e9:.3f} GB = {(rb + wb) / 1e9:.3f} GB per launch, "
             f"{(rb + wb) / alg:.3f} x the algorithmic {alg / 1e9:.3f} GB (reads {rb / (alg / 2):.3f} x, "
             f"writes {wb / (alg / 2):.3f} x).",
+            "",
+        ]
+    vpath = os.path.join(outdir, "prof_ens_valu", "ens_valu_counter_collection.csv")
+    if os.path.exists(vpath):
+        c = {}
+        for r in csv.DictReader(open(vpath)):
+            if r["Kernel_Name"].startswith(ENS_KERNEL):
+                c.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        med = {k: statistics.median(v) for k, v in c.items()}
+        per_xcd = med["GRBM_GUI_ACTIVE"] / XCC_NUM
+        lines += [
+            "Vector-ALU activity (one counter pass, medians over the ensemble kernel's dispatches; definitions as "
+            "in `k_step_valu_256cube.md`):",
+            "",
+            "    " + CMD_ENS_VALU,
+            "",
+            f"VALU instructions per site (SQ_INSTS_VALU x 64 / sites, idle lanes included) "
+            f"{med['SQ_INSTS_VALU'] * 64 / e['sites']:.0f}; quad-cycles per VALU instruction "
+            f"{med['SQ_ACTIVE_INST_VALU'] / med['SQ_INSTS_VALU']:.3f}; VALU busy "
+            f"{100 * med['SQ_ACTIVE_INST_VALU'] / CU_NUM / per_xcd:.0f} %.",
             "",
         ]
     with open(os.path.join(ROOT, "profiles", "k_ensemble_step_mixed320.md"), "w") as fh:

@@ -146,3 +146,29 @@ def test_in_place_external_buffer_is_half_the_size():
     assert np.array_equal(out[0][1], out[1][1])
     with pytest.raises(_lib.CmfError):
         Lattice(q, shape, storage="f32", in_place=True, external=(base, one - 256))
+
+
+def test_in_place_autotune_and_resume_keep_the_trajectory():
+    """Autotuning from the swapped slot order restores that state, and a run
+    saved and resumed (populations, step index) continues it: the
+    populations equal the pull lattice's bit for bit (they do not depend on
+    the launch shape)."""
+    q, shape = 27, (24, 20, 18)
+    f0 = _state(q, shape, 61)
+    res = []
+    for in_place in (False, True):
+        kw = dict(storage="f32", tau=0.7, kT=1e-4, seed=9, in_place=in_place)
+        with Lattice(q, shape, **kw) as lat:
+            lat.set_populations(f0)
+            lat.step(3)
+            lat.autotune(steps_per_trial=3)
+            assert lat.step_index == 3
+            lat.step(6)
+            saved, at = lat.get_populations(), lat.step_index
+        with Lattice(q, shape, **kw) as lat:
+            lat.set_populations(saved)
+            lat.step_index = at
+            lat.step(35)
+            res.append((saved, lat.get_populations()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
