@@ -40,7 +40,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("paper_2602_16486_amd/csrc/cmflb_kernels.hip",
+KERNEL_SOURCES = ("paper_2602_16486_amd/csrc/cmflb_step.h",
+                  "paper_2602_16486_amd/csrc/cmflb_step_pull.hip",
                   "paper_2602_16486_amd/csrc/cmflb_device.h",
                   "paper_2602_16486_amd/csrc/cmflb_internal.h",
                   "paper_2602_16486_amd/csrc/cmflb_d3q19.h")

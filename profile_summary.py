@@ -395,7 +395,7 @@ CMD_VALU0 = CMD_VALU.replace("prof_valu", "prof_valu0").replace("-o valu", "-o v
     "--no-ensemble", "--no-ensemble --kT 0")
 CMD_ASM = ("/opt/rocm/lib/llvm/bin/clang++ -x hip --offload-arch=gfx950 --offload-device-only -O3 -std=c++17 "
            "-ffp-contract=on -I include -Xclang -target-feature -Xclang -packed-fp32-ops -S "
-           "paper_2602_16486_amd/csrc/cmflb_kernels.hip -o out/kernels.s")
+           "paper_2602_16486_amd/csrc/cmflb_step_pull.hip -o out/kernels.s")
 # opcode classes of the static budget
 CLASSES = [
     ("Philox4x32-10 (64-bit products, 3-input xor)", ("v_mad_u64_u32", "v_bitop3_b32")),
