@@ -139,12 +139,15 @@ int cmf_device_count(void);
  * [0, 2], N >= 2^31, nx >= 2^28), CMF_ENOMEM, CMF_EHIP. */
 int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
 
-/* As cmf_create, but the two population buffers live in caller-owned device
- * memory (for instance a torch tensor): dev_ptr, 256-byte aligned, on the
- * current device, holding at least cmf_external_bytes(desc) bytes; buffer 0
- * starts at dev_ptr, buffer 1 half-way.  Their contents are the library's
- * internal storage (deviations f - w rho0, scaled for 16-bit storage, in a
- * row-interleaved order), not the canonical populations: read those with
+/* As cmf_create, but the two population buffers (one with
+ * CMF_FLAG_IN_PLACE) live in caller-owned device memory (for instance a
+ * torch tensor): dev_ptr, 256-byte aligned, on the current device, holding
+ * at least cmf_external_bytes(desc) bytes; buffer 0 starts at dev_ptr,
+ * buffer 1 half-way.  Their contents are the library's internal storage
+ * (deviations f - w rho0, scaled for 16-bit storage, in a row-interleaved
+ * order; with in-place streaming, in the natural slot order after an even
+ * number of steps and in the swapped one after an odd number), not the
+ * canonical populations: read those with
  * cmf_get_populations.  The lattice writes the rest state into the buffers,
  * never frees them, and the caller
  * keeps it alive until cmf_destroy.  Statistics scratch is still allocated by
@@ -153,9 +156,10 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
 int cmf_create_external(const cmf_desc *desc, void *dev_ptr, size_t bytes, void *hip_stream,
                         cmf_lattice **out);
 
-/* Bytes cmf_create_external needs for `desc` (two population buffers, each
- * q x N elements of the storage type rounded up to 256 bytes); 0 when the
- * descriptor is invalid. */
+/* Bytes cmf_create_external needs for `desc` (two population buffers, or
+ * one with CMF_FLAG_IN_PLACE, each q x N elements of the storage type
+ * rounded up to 256 bytes); 0 when the descriptor is invalid or asks for
+ * in-place streaming where it is not supported. */
 size_t cmf_external_bytes(const cmf_desc *desc);
 
 /* Release all device memory the lattice allocated (synchronises its
@@ -236,7 +240,8 @@ int cmf_set_launch(cmf_lattice *lat, int32_t block, int32_t grid);
  * variable CMFLB_TUNE_CACHE names a file, entries are also read from and
  * appended to it.  Up to `cap` trials are written to `trials` (may be NULL);
  * *n_out (may be NULL) receives the number of trials.  Needs one temporary
- * buffer the size of the population state.  Synchronous. */
+ * buffer the size of the population state (also with CMF_FLAG_IN_PLACE, for
+ * the duration of the call).  Synchronous. */
 int cmf_autotune(cmf_lattice *lat, int32_t steps_per_trial, cmf_launch *trials,
                  int32_t cap, int32_t *n_out);
 
