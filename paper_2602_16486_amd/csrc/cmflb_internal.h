@@ -170,7 +170,7 @@ constexpr int kLineBytes = 128;
 // XCDs of an MI355X (the tile maps assume round-robin dispatch over them)
 constexpr int kXcds = 8;
 // adjacent ensemble tiles kept on one XCD
-constexpr int kXcdChunk = 32;
+constexpr int kXcdChunk = 8;
 hipError_t launch_ensemble_step(int storage, bool general, const void *reps,
                                 const int32_t *tile_rep, int ntiles,
                                 const void *src, void *dst,
