@@ -172,3 +172,20 @@ def test_in_place_autotune_and_resume_keep_the_trajectory():
             res.append((saved, lat.get_populations()))
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("q,shape", [(9, (70, 40)), (19, (40, 12, 10)), (27, (40, 12, 10))])
+@pytest.mark.parametrize("block,grid", [(64, 4), (128, 1 << 20), (256, 33)])
+def test_in_place_equals_pull_in_every_launch_shape(q, shape, block, grid):
+    """Persistent grids (workgroups striding over the row tiles) and one
+    workgroup per tile, with row tiles shorter than and as long as a row."""
+    f = _state(q, shape, 71)
+    out = []
+    for in_place in (False, True):
+        with Lattice(q, shape, storage="f32", tau=0.66, kT=5e-5, seed=4, in_place=in_place) as lat:
+            lat.set_launch(block, grid)
+            lat.set_populations(f)
+            lat.step(9)
+            out.append((lat.get_populations(), lat.stats()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
