@@ -416,7 +416,7 @@ int cmf_ensemble_set_tiles(cmf_ensemble *ens, int32_t spt9, int32_t spt3d);
 
 /* Autotuner of the tile shape (the batched-ensemble configuration of the
  * benchmark asks for tuned tiles): time spt9 in {1, 2, 3, 4, 6, 8} (when
- * there are D2Q9 replicas) x spt3d in {1, 2, 3, 4} (when there are 3-D
+ * there are D2Q9 replicas) x spt3d in {1, 2, 3, 4, 6, 8} (when there are 3-D
  * replicas) with `steps_per_trial` direct steps each (after one untimed
  * step; a step = fused kernel + per-replica statistics), then restore the
  * populations, step counter and statistics rings exactly and keep the

@@ -1882,7 +1882,7 @@ int cmf_ensemble_autotune(cmf_ensemble *E, int32_t steps_per_trial, cmf_ensemble
   bool has2d = false, has3d = false;
   for (const auto &rp : E->reps) (rp.desc.q == 9 ? has2d : has3d) = true;
   std::vector<int> c9 = has2d ? std::vector<int>{1, 2, 3, 4, 6, 8} : std::vector<int>{E->spt9};
-  std::vector<int> c3 = has3d ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{E->spt3d};
+  std::vector<int> c3 = has3d ? std::vector<int>{1, 2, 3, 4, 6, 8} : std::vector<int>{E->spt3d};
   // snapshot: current arena, step counter, statistics rings
   const size_t series_bytes = sizeof(double) * kSeriesStride * E->cap * E->n;
   void *saved = nullptr, *saved_series = nullptr;

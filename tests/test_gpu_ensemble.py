@@ -170,8 +170,8 @@ def test_autotune_restores_state_and_keeps_results():
         ens.step(3)
         before = [ens.get_populations(k) for k in range(len(REPLICAS))]
         trials = ens.autotune(steps_per_trial=2)
-        # D2Q9 and 3-D replicas present: 6 x 4 shapes
-        assert len(trials) == 24 and all(t[2] > 0 for t in trials)
+        # D2Q9 and 3-D replicas present: 6 x 6 shapes
+        assert len(trials) == 36 and all(t[2] > 0 for t in trials)
         best = min(trials, key=lambda t: t[2])
         assert ens.tiles == best[:2]
         assert ens.step_index == 3
@@ -208,7 +208,7 @@ def test_autotune_without_statistics():
         ens.step(2)
         before = [ens.get_populations(k) for k in range(len(REPLICAS))]
         trials = ens.autotune(steps_per_trial=1)
-        assert len(trials) == 24
+        assert len(trials) == 36
         assert ens.step_index == 2
         for k in range(len(REPLICAS)):
             assert np.array_equal(ens.get_populations(k), before[k])
