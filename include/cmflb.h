@@ -82,10 +82,12 @@ enum {
 #define CMF_FLAG_NO_GRAPH 1u   /* enqueue launches directly, never capture */
 #define CMF_FLAG_NO_STATS 2u   /* skip the per-step statistics finalize */
 #define CMF_FLAG_IN_PLACE 4u   /* in-place (AA) streaming on one population
-                                  buffer instead of two: half the population
-                                  memory, the same results bit for bit
-                                  (single lattices whose z planes of q ny nx
-                                  values take below 4 GiB) */
+                                  buffer instead of two: the streaming of
+                                  eq. (streaming) in another storage order,
+                                  half the population memory, the same
+                                  results bit for bit (single lattices whose
+                                  z planes of q ny nx values take below
+                                  4 GiB) */
 
 typedef struct {
   int32_t q;         /* 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27) */
