@@ -147,7 +147,9 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
  * at least cmf_external_bytes(desc) bytes; buffer 0 starts at dev_ptr,
  * buffer 1 half-way.  Their contents are the library's internal storage
  * (deviations f - w rho0, scaled for 16-bit storage, in a row-interleaved
- * order; with in-place streaming, in the natural slot order after an even
+ * order: for lattice row y + ny z, q rows of nx values, the populations of
+ * the 3-D lattices ordered by their velocities (c_z, c_y, c_x), those of
+ * D2Q9 in the paper's order; with in-place streaming, in the natural slot order after an even
  * number of steps and in the swapped one after an odd number), not the
  * canonical populations: read those with
  * cmf_get_populations.  The lattice writes the rest state into the buffers,

@@ -70,11 +70,11 @@ __global__ __launch_bounds__(256) void k_finalize(
 // ---------------------------------------------------------------------------
 // element offset of population i at site s in the population buffer (the
 // row-interleaved layout, or one array per population when cp.pitch > 0)
-template <int Q>
+template <class L>
 __device__ __forceinline__ int64_t pop_site_offset(const ConvParams &cp, int i,
                                                    int64_t s) {
   if (cp.pitch > 0) return (int64_t)i * cp.pitch + s;
-  return pop_row_offset<Q>(i, s / cp.nx, cp.nx) + s % cp.nx;
+  return pop_row_offset<L>(i, s / cp.nx, cp.nx) + s % cp.nx;
 }
 
 template <class L>
@@ -95,9 +95,9 @@ __device__ __forceinline__ int64_t shifted_site(const ConvParams &cp, int64_t s,
 // buffer, for the buffer's layout (cp.layout)
 template <class L>
 __device__ __forceinline__ int64_t state_offset(const ConvParams &cp, int i, int64_t s) {
-  if (cp.layout == kLayoutNatural) return pop_site_offset<L::Q>(cp, i, s);
+  if (cp.layout == kLayoutNatural) return pop_site_offset<L>(cp, i, s);
   const int slot = cp.layout == kLayoutSwapped ? opposite<L>(i) : i;
-  return pop_site_offset<L::Q>(cp, slot, shifted_site<L>(cp, s, i, -1));
+  return pop_site_offset<L>(cp, slot, shifted_site<L>(cp, s, i, -1));
 }
 
 // d_eq = f_eq(rho, u) - w rho0 = T(u)^-1 (rho e_0 - rho0 G(u)), evaluated at

@@ -15,7 +15,8 @@
 //
 // Memory layout: populations are stored as deviations d_i = f_i - w_i rho0
 // in a row-interleaved structure of arrays (pop_row_offset): for lattice row
-// (y, z) the Q rows of nx values are contiguous.  The buffer of step t
+// (y, z) the Q rows of nx values are contiguous, in the order of the
+// velocities (c_z, c_y, c_x) (pop_slot).  The buffer of step t
 // holds post-collision values of step t - 1 at their source site; step t
 // pulls d_i(x - c_i), collides, and writes d*_i(x) to the other buffer
 // (two-buffer pull scheme), or, with in-place streaming, the even and odd
@@ -489,7 +490,7 @@ __device__ __forceinline__ void load_site(R *d, const S *__restrict__ src,
     }
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const S *base = src + pop_row_offset<L::Q>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
+    const S *base = src + pop_row_offset<L>(i, srow[L::cy[i] + 1][L::cz[i] + 1], nx);
     const float sc = scale[weight_class<L>(i)];
     // (the condition is a compile-time constant once the loop is unrolled)
     if (NT_C0 && L::cx[i] == 0)
@@ -508,7 +509,7 @@ __device__ __forceinline__ void store_site(const R *d, S *__restrict__ dst,
   using ST = Store<S, R>;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    S *base = dst + pop_row_offset<L::Q>(i, row, nx);
+    S *base = dst + pop_row_offset<L>(i, row, nx);
     ST::template store<NT>(base + (uint32_t)x, d[i], iscale[weight_class<L>(i)]);
   }
 }
@@ -539,7 +540,7 @@ __device__ __forceinline__ void load_site_buf(R *d, const S *__restrict__ src,
   const uint32_t rowb = (uint32_t)nx * B;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const uint32_t soff = (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)i) * rowb;
+    const uint32_t soff = (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)pop_slot<L>(i)) * rowb;
     const float sc = scale[weight_class<L>(i)];
     if (NT_C0 && L::cx[i] == 0)
       d[i] = ST::from_bits(buf_load<S, true>(rs[L::cz[i] + 1], xs[1], soff), sc);
@@ -561,7 +562,7 @@ __device__ __forceinline__ void store_site_buf(const R *d, S *__restrict__ dst,
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
     buf_store<S, NT>(ST::to_bits(d[i], iscale[weight_class<L>(i)]), r, (uint32_t)x * B,
-                     (blk + (uint32_t)i) * rowb);
+                     (blk + (uint32_t)pop_slot<L>(i)) * rowb);
 }
 
 struct TileXY {
@@ -632,7 +633,7 @@ __device__ __forceinline__ void load_site_aa(R *d, const S *buf, const float *sc
     const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + (int64_t)z * plane, pbytes);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-      d[i] = ST::from_bits(buf_load<S, NT>(r, (uint32_t)x * B, ((uint32_t)y * L::Q + i) * rowb),
+      d[i] = ST::from_bits(buf_load<S, NT>(r, (uint32_t)x * B, ((uint32_t)y * L::Q + pop_slot<L>(i)) * rowb),
                            scale[weight_class<L>(i)]);
   } else {
     __amdgpu_buffer_rsrc_t rs[3];
@@ -648,7 +649,8 @@ __device__ __forceinline__ void load_site_aa(R *d, const S *buf, const float *sc
     for (int a = 0; a < 3; ++a) ys[a] = (uint32_t)wrap_sub(y, a - 1, ny);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      const uint32_t soff = (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)opposite<L>(i)) * rowb;
+      const uint32_t soff =
+          (ys[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)pop_slot<L>(opposite<L>(i))) * rowb;
       const float sc = scale[weight_class<L>(i)];
       if (NT && L::cx[i] == 0)
         d[i] = ST::from_bits(buf_load<S, true>(rs[L::cz[i] + 1], xs[1], soff), sc);
@@ -671,7 +673,7 @@ __device__ __forceinline__ void store_site_aa(const R *d, S *buf, const float *i
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
       buf_store<S, NT>(ST::to_bits(d[i], iscale[weight_class<L>(i)]), r, (uint32_t)x * B,
-                       ((uint32_t)y * L::Q + (uint32_t)opposite<L>(i)) * rowb);
+                       ((uint32_t)y * L::Q + (uint32_t)pop_slot<L>(opposite<L>(i))) * rowb);
   } else {
     // destination plane z + c_z, row y + c_y, column x + c_x (index c + 1)
     __amdgpu_buffer_rsrc_t rd[3];
@@ -687,7 +689,7 @@ __device__ __forceinline__ void store_site_aa(const R *d, S *buf, const float *i
     for (int a = 0; a < 3; ++a) yd[a] = (uint32_t)wrap_sub(y, 1 - a, ny);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      const uint32_t soff = (yd[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)i) * rowb;
+      const uint32_t soff = (yd[L::cy[i] + 1] * (uint32_t)L::Q + (uint32_t)pop_slot<L>(i)) * rowb;
       const R v = d[i];
       if (NT && L::cx[i] == 0)
         buf_store<S, true>(ST::to_bits(v, iscale[weight_class<L>(i)]), rd[L::cz[i] + 1], xd[1], soff);

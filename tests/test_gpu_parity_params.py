@@ -141,7 +141,9 @@ def test_16bit_storage_scale_follows_rho0(q, shape, rho0, storage):
     divided by s_i = 2^ceil(log2 sigma_i), sigma_i = sqrt(rho0 kT w_i / c_s^2)
     (the documented storage scale), rounded to nearest even.  Read from
     caller-owned buffers in the row-interleaved layout: element
-    ((y + ny z) q + i) nx + x, holding the value pulled by site x + c_i."""
+    ((y + ny z) q + slot_i) nx + x, slot_i the rank of population i in the
+    order of its velocity (c_z, c_y, c_x) on the 3-D lattices and i on D2Q9,
+    holding the value pulled by site x + c_i."""
     import torch
     kT = 1e-4
     n = W.n_sites(shape)
@@ -152,14 +154,16 @@ def test_16bit_storage_scale_follows_rho0(q, shape, rho0, storage):
     s = 2.0 ** np.ceil(np.log2(np.sqrt(rho0 * kT * w * 3.0)))
     dt = torch.float16 if storage == "f16" else torch.bfloat16
     vals = torch.from_numpy(words.view(np.int16).copy()).view(dt).float().numpy()
-    vals = vals.astype(np.float64).reshape(ny * nz, q, nx)  # [row][i][x]
+    vals = vals.astype(np.float64).reshape(ny * nz, q, nx)  # [row][slot][x]
+    pos = (c[:, 0] + 1) + 3 * (c[:, 1] + 1) + 9 * (c[:, 2] + 1)
+    slot = np.argsort(np.argsort(pos)) if q != 9 else np.arange(q)
     site = np.arange(n)
     x, y, z = site % nx, (site // nx) % ny, site // (nx * ny)
     got = np.zeros((q, n))
     for i in range(q):
         # the slot read by site s for population i sits at s - c_i
         xs, ys, zs = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
-        got[i] = vals[ys + ny * zs, i, xs] * s[i]
+        got[i] = vals[ys + ny * zs, slot[i], xs] * s[i]
     dev = f - rho0 * w[:, None]
     # FP64 -> FP32 -> 16-bit, both rounding to nearest: within one 16-bit
     # rounding of the scaled deviation (plus FP16 subnormal spacing)
