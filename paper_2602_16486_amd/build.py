@@ -18,8 +18,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/cmflb_step_pull.hip", "csrc/cmflb_step_aa.hip", "csrc/cmflb_kernels.hip",
-           "csrc/cmflb_capi.hip"]
+SOURCES = ["csrc/cmflb_step_pull.hip", "csrc/cmflb_step_aa.hip", "csrc/cmflb_ensemble.hip",
+           "csrc/cmflb_kernels.hip", "csrc/cmflb_capi.hip"]
 ARCH = "gfx950"
 
 

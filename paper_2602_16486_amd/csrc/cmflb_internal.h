@@ -91,7 +91,8 @@ struct ConvParams {
 
 enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
-// launchers (defined in cmflb_kernels.hip); all return hipError_t
+// launchers (defined in cmflb_kernels.hip, the ensemble's in cmflb_ensemble.hip);
+// all return hipError_t
 // nt: non-temporal population stores (rows of whole cache lines), else plain
 // The step index of a launch is *step_ptr + step_off: runs of steps
 // captured in a graph pass offsets 0, 1, ... and advance *step_ptr once at

@@ -1,9 +1,9 @@
 // cmflb_step.h -- the fused step of libcmflb for gfx950: the per-site
 // collision (D2Q9, D3Q19, D3Q27), the block reduction of its statistics, the
 // single-lattice step kernels (two-buffer pull and in-place pair) and their
-// launch templates.  Included by cmflb_kernels.hip (the ensemble step
-// inlines the same collision) and by the two translation units that
-// instantiate the launches.
+// launch templates.  Included by cmflb_ensemble.hip (the ensemble step
+// inlines the same collision), by cmflb_kernels.hip (launch_step) and by the
+// two translation units that instantiate the launches.
 //
 // Method: De Rosis & Zhou, "A fluctuating lattice Boltzmann formulation based
 // on orthogonal central moments" (arXiv 2602.16486), Sec. 2.2 (D2Q9),
