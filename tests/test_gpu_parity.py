@@ -423,11 +423,18 @@ def test_mass_and_momentum_conserved_fp64():
     (19, (256, 256, 256), "f32", None),
     (9, (1024, 1024), "f32", None),
     (27, (1024, 1024, 1024), "f32", None),  # largest cube whose two buffers fit (232 GB)
+    # z planes of 4 GiB or more: the step's 64-bit-addressed form
+    (9, (12288, 10240), "f32", None),       # one 4.5 GB plane
+    (27, (6400, 6272, 2), "f32", None),     # 4.3 GB planes
+    (27, (9216, 8704, 2), "f16", 8192),
+    (19, (8192, 7680, 2), "f32", None),     # 4.8 GB planes
 ])
 def test_full_size_sampled_one_step(q, shape, storage, grid):
-    """Full-size lattices in the launch shapes the benchmark times, and the
+    """Full-size lattices in the launch shapes the benchmark times, the
     largest D3Q27 cube that fits (2^30 sites, 116 GB per buffer, element
-    offsets beyond 2^32): after 20 steps from rest, one more step is checked
+    offsets beyond 2^32), and boxes whose z planes (Q ny nx values) span
+    4 GiB or more, which the step addresses with 64-bit pointers instead of
+    32-bit buffer offsets: after 20 steps from rest, one more step is checked
     at sampled sites (random plus every box corner/edge midpoint) against the
     oracle's single-site collision of the gathered pre-collision populations.
     16-bit storage adds one rounding of each deviation to the storage
