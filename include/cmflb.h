@@ -257,7 +257,12 @@ int cmf_autotune(cmf_lattice *lat, int32_t steps_per_trial, cmf_launch *trials,
  * 256-byte aligned and holding q x N elements of the storage type in the
  * library's internal layout -- the two halves of a cmf_create_external
  * buffer (deviations f - w rho0, scaled for 16-bit storage, row-interleaved;
- * write and read them through such a lattice).  `step` (in [0, 2^56)) is
+ * write and read them through such a lattice).  Each buffer, and
+ * `stats_dev`, must lie in one device allocation known to HIP (hipMalloc,
+ * or an allocator built on it such as PyTorch's) with room for its data
+ * from the pointer to the allocation's end; the call checks this on the
+ * host (hipPointerGetAttributes, hipMemGetAddressRange) and returns
+ * CMF_EINVAL otherwise.  `step` (in [0, 2^56)) is
  * the index whose noise the step draws; the launch shape is (`block`,
  * `grid`) as in cmf_set_launch, with grid at most 65536 (larger grids are
  * rejected: the scratch holds the partial sums of that many workgroups).
@@ -268,7 +273,7 @@ int cmf_autotune(cmf_lattice *lat, int32_t steps_per_trial, cmf_launch *trials,
  * GPU shares it, so calls that overlap on one GPU (different streams or
  * threads) race and must be serialised by the caller.  Asynchronous on
  * `hip_stream` (NULL: the null stream); launches kernels only (no memset,
- * no allocation).  Errors: CMF_EINVAL (desc, buffers, step, launch shape),
+ * no allocation).  Errors: CMF_EINVAL (desc, buffers and their sizes, step, launch shape),
  * CMF_EUNSUPPORTED (device index >= 64), CMF_EHIP. */
 int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst, int64_t step,
                      int32_t block, int32_t grid, double *stats_dev, void *hip_stream);

@@ -1465,6 +1465,31 @@ int scratch_address(double **out) {
   *out = g_scratch_dev[dev];
   return CMF_OK;
 }
+
+// `p` must point into a device allocation of the current device with at
+// least `bytes` bytes from p to the allocation's end (host-side queries
+// only: a wrong pointer or a short buffer becomes CMF_EINVAL instead of a
+// kernel access out of bounds).
+int check_device_span(const void *p, size_t bytes, const char *what) {
+  hipPointerAttribute_t attr;
+  int dev = 0;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(CMF_EINVAL, "%s is not device memory of the current device", what);
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CMF_EINVAL, "%s: the allocation holding it is not known to HIP", what);
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base), a = reinterpret_cast<uintptr_t>(p);
+  if (a < b || a - b > size || size - (a - b) < bytes)
+    return fail(CMF_EINVAL, "%s: %zu bytes from it to the end of its allocation, the step needs %zu",
+                what, a < b || a - b > size ? (size_t)0 : size - (a - b), bytes);
+  return CMF_OK;
+}
 }  // namespace
 
 extern "C" int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst, int64_t step,
@@ -1486,6 +1511,13 @@ extern "C" int cmf_step_noalloc(const cmf_desc *desc, const void *src, void *dst
     return fail(CMF_EINVAL,
                 "grid %d exceeds %d: the scratch holds the partial sums of at most %d workgroups",
                 grid, kNoAllocMaxGrid, kNoAllocMaxGrid);
+  const size_t state_bytes =
+      (size_t)desc->q * desc->nx * desc->ny * desc->nz * storage_bytes(desc->storage);
+  rc = check_device_span(src, state_bytes, "src");
+  if (rc == CMF_OK) rc = check_device_span(dst, state_bytes, "dst");
+  if (rc == CMF_OK && stats_dev)
+    rc = check_device_span(stats_dev, kSeriesStride * sizeof(double), "stats_dev");
+  if (rc != CMF_OK) return rc;
   double *scr = nullptr;
   rc = scratch_address(&scr);
   if (rc != CMF_OK) return rc;

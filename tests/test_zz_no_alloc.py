@@ -103,9 +103,29 @@ def test_noalloc_rejects_bad_arguments():
         ((base, base + half, 1 << 56, 64, 10), b"outside [0, 2^56)"),
         ((base, base + half, -1, 64, 10), b"outside [0, 2^56)"),
     ]
+    # host memory (256-byte aligned, so that only the memory check refuses it)
+    host = np.zeros(nb + 256, dtype=np.uint8)
+    hbase = host.ctypes.data + (-host.ctypes.data) % 256
+    cases += [
+        ((hbase, base + half, 0, 64, 10), b"src is not device memory"),
+        ((base, hbase, 0, 64, 10), b"dst is not device memory"),
+    ]
+    # a destination too close to the end of its allocation (torch's segment
+    # holding the tensor, one hipMalloc): 256 bytes short of the state
+    state = q * W.n_sites(shape) * 4
+    seg = [g for g in torch.cuda.memory_snapshot()
+           if g["address"] <= base < g["address"] + g["total_size"]]
+    if seg:
+        end = seg[0]["address"] + seg[0]["total_size"]
+        short = (end - state + 255) // 256 * 256 + 256
+        assert base + half <= short < end and end - short < state
+        cases.append(((base, short, 0, 64, 10), b"dst: "))
     for (src, dst, step, block, grid), msg in cases:
         rc = lib.cmf_step_noalloc(ctypes.byref(d), ctypes.c_void_p(src), ctypes.c_void_p(dst), step,
                                   block, grid, None, None)
         assert rc == _lib.CMF_EINVAL and msg in lib.cmf_last_error(), (msg, lib.cmf_last_error())
+    rc = lib.cmf_step_noalloc(ctypes.byref(d), ctypes.c_void_p(base), ctypes.c_void_p(base + half), 0,
+                              64, 10, ctypes.c_void_p(hbase), None)
+    assert rc == _lib.CMF_EINVAL and b"stats_dev is not device memory" in lib.cmf_last_error()
     torch.cuda.synchronize()
     assert not t.any().item()  # nothing was launched
