@@ -156,7 +156,9 @@ int cmf_create(const cmf_desc *desc, void *hip_stream, cmf_lattice **out);
  * never frees them, and the caller
  * keeps it alive until cmf_destroy.  Statistics scratch is still allocated by
  * the library.  Errors: those of cmf_create, CMF_EINVAL when dev_ptr is NULL,
- * misaligned, too small or not device memory of the current device. */
+ * misaligned, too small (the `bytes` given, or what its allocation holds
+ * from dev_ptr on, checked with hipMemGetAddressRange) or not device memory
+ * of the current device. */
 int cmf_create_external(const cmf_desc *desc, void *dev_ptr, size_t bytes, void *hip_stream,
                         cmf_lattice **out);
 
@@ -308,7 +310,10 @@ int cmf_stats(cmf_lattice *lat, cmf_moments *out, int64_t cap,
  * to FP32) into device buffers on the lattice's device: rho_dev (N floats)
  * and u_dev (3 x N floats, u_x block first; u_z = 0 on D2Q9); both are
  * owned by the caller.  Either pointer may be NULL.  Asynchronous on the
- * lattice's stream.  Errors: CMF_EINVAL (NULL lattice), CMF_EHIP. */
+ * lattice's stream.  Errors: CMF_EINVAL (NULL lattice; a buffer that is not
+ * device memory of the current device or whose allocation holds fewer
+ * bytes from the pointer on than it receives, checked on the host before
+ * any launch), CMF_EHIP. */
 int cmf_sample_macro(cmf_lattice *lat, void *rho_dev, void *u_dev);
 
 /* The density and velocity of the current pre-collision state, computed on

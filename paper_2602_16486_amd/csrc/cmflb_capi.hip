@@ -701,6 +701,31 @@ size_t buffer_bytes(const cmf_desc *d) {
   return ((size_t)d->q * d->nx * d->ny * d->nz * storage_bytes(d->storage) + 255) / 256 * 256;
 }
 
+// `p` must point into a device allocation of the current device with at
+// least `bytes` bytes from p to the allocation's end (host-side queries
+// only: a wrong pointer or a short buffer becomes CMF_EINVAL instead of a
+// kernel access out of bounds).
+int check_device_span(const void *p, size_t bytes, const char *what) {
+  hipPointerAttribute_t attr;
+  int dev = 0;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(CMF_EINVAL, "%s is not device memory of the current device", what);
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CMF_EINVAL, "%s: the allocation holding it is not known to HIP", what);
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base), a = reinterpret_cast<uintptr_t>(p);
+  if (a < b || a - b > size || size - (a - b) < bytes)
+    return fail(CMF_EINVAL, "%s: %zu bytes from it to the end of its allocation, %zu needed",
+                what, a < b || a - b > size ? (size_t)0 : size - (a - b), bytes);
+  return CMF_OK;
+}
+
 // population buffers of a lattice: one with in-place streaming, else two
 int buffer_count(const cmf_desc *d) { return (d->flags & CMF_FLAG_IN_PLACE) ? 1 : 2; }
 
@@ -729,13 +754,8 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
       return fail(CMF_EINVAL, "external buffer is not 256-byte aligned");
     if (ext_bytes < need)
       return fail(CMF_EINVAL, "external buffer holds %zu bytes, the lattice needs %zu", ext_bytes, need);
-    hipPointerAttribute_t attr;
-    int dev = 0;
-    if (hipPointerGetAttributes(&attr, ext) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-        hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
-      (void)hipGetLastError();
-      return fail(CMF_EINVAL, "external buffer is not device memory of the current device");
-    }
+    rc = check_device_span(ext, need, "external buffer");
+    if (rc != CMF_OK) return rc;
   }
   cmf_lattice *L = new cmf_lattice();
   L->desc = *desc;
@@ -1260,6 +1280,9 @@ int cmf_stats(cmf_lattice *L, cmf_moments *out, int64_t cap, int64_t *n_out) {
 
 int cmf_sample_macro(cmf_lattice *L, void *rho_dev, void *u_dev) {
   if (!L) return fail(CMF_EINVAL, "lattice is NULL");
+  int rc = rho_dev ? check_device_span(rho_dev, sizeof(float) * L->N, "rho_dev") : CMF_OK;
+  if (rc == CMF_OK && u_dev) rc = check_device_span(u_dev, sizeof(float) * 3 * L->N, "u_dev");
+  if (rc != CMF_OK) return rc;
   HIP_TRY(launch_macro(L->q, L->storage, conv(L), L->buf[L->parity], (float *)rho_dev,
                        (float *)u_dev, L->stream));
   return CMF_OK;
@@ -1463,31 +1486,6 @@ int scratch_address(double **out) {
     g_scratch_dev[dev] = static_cast<double *>(ptr);
   }
   *out = g_scratch_dev[dev];
-  return CMF_OK;
-}
-
-// `p` must point into a device allocation of the current device with at
-// least `bytes` bytes from p to the allocation's end (host-side queries
-// only: a wrong pointer or a short buffer becomes CMF_EINVAL instead of a
-// kernel access out of bounds).
-int check_device_span(const void *p, size_t bytes, const char *what) {
-  hipPointerAttribute_t attr;
-  int dev = 0;
-  if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-      hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
-    (void)hipGetLastError();
-    return fail(CMF_EINVAL, "%s is not device memory of the current device", what);
-  }
-  hipDeviceptr_t base = nullptr;
-  size_t size = 0;
-  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(CMF_EINVAL, "%s: the allocation holding it is not known to HIP", what);
-  }
-  const uintptr_t b = reinterpret_cast<uintptr_t>(base), a = reinterpret_cast<uintptr_t>(p);
-  if (a < b || a - b > size || size - (a - b) < bytes)
-    return fail(CMF_EINVAL, "%s: %zu bytes from it to the end of its allocation, the step needs %zu",
-                what, a < b || a - b > size ? (size_t)0 : size - (a - b), bytes);
   return CMF_OK;
 }
 }  // namespace

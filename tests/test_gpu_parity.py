@@ -613,6 +613,20 @@ def test_external_buffers_from_torch():
     host = np.zeros(nbytes, dtype=np.uint8)
     with pytest.raises(_lib.CmfError):
         Lattice(q, shape, storage="f32", external=(host.ctypes.data, nbytes))
+    # a claimed size beyond the end of the allocation (torch's segment, one
+    # hipMalloc) is refused before the lattice writes its rest state
+    end = _segment_end(torch, base)
+    near = (end - nbytes + 255) // 256 * 256 + 256
+    with pytest.raises(_lib.CmfError, match="to the end of its allocation"):
+        Lattice(q, shape, storage="f32", external=(near, nbytes))
+
+
+def _segment_end(torch, ptr):
+    """End address of the torch allocator segment (one hipMalloc) holding ptr."""
+    seg = [g for g in torch.cuda.memory_snapshot()
+           if g["address"] <= ptr < g["address"] + g["total_size"]]
+    assert len(seg) == 1, "the pointer's segment is not in torch's memory snapshot"
+    return seg[0]["address"] + seg[0]["total_size"]
 
 
 @pytest.mark.parametrize("q,shape", [(9, (33, 17)), (19, (20, 12, 9)), (27, (20, 12, 9))])
@@ -642,6 +656,17 @@ def test_sample_macro_into_torch_buffers(q, shape):
     assert np.array_equal(got_u[:3 * n].reshape(3, n), u64.astype(np.float32))
     assert np.all(got_r[n:] == -7.0) and np.all(got_u[3 * n:] == -7.0)
     assert np.array_equal(r2_t.cpu().numpy(), got_r[:n])
+    # host memory, or a buffer shorter than N floats before the end of its
+    # allocation, is refused before any launch
+    host = np.zeros(3 * n, dtype=np.float32)
+    short = _segment_end(torch, r2_t.data_ptr()) - 4 * (n - 1)
+    with Lattice(q, shape, storage="f32") as lat:
+        with pytest.raises(_lib.CmfError, match="rho_dev is not device memory"):
+            lat.sample_macro(host.ctypes.data, 0)
+        with pytest.raises(_lib.CmfError, match="u_dev is not device memory"):
+            lat.sample_macro(0, host.ctypes.data)
+        with pytest.raises(_lib.CmfError, match="to the end of its allocation"):
+            lat.sample_macro(short, 0)
 
 
 def test_stream_copy_diagnostic():

@@ -115,11 +115,11 @@ def test_noalloc_rejects_bad_arguments():
     state = q * W.n_sites(shape) * 4
     seg = [g for g in torch.cuda.memory_snapshot()
            if g["address"] <= base < g["address"] + g["total_size"]]
-    if seg:
-        end = seg[0]["address"] + seg[0]["total_size"]
-        short = (end - state + 255) // 256 * 256 + 256
-        assert base + half <= short < end and end - short < state
-        cases.append(((base, short, 0, 64, 10), b"dst: "))
+    assert len(seg) == 1, "the tensor's segment is not in torch's memory snapshot"
+    end = seg[0]["address"] + seg[0]["total_size"]
+    short = (end - state + 255) // 256 * 256 + 256
+    assert base + half <= short < end and end - short < state
+    cases.append(((base, short, 0, 64, 10), b"dst: "))
     for (src, dst, step, block, grid), msg in cases:
         rc = lib.cmf_step_noalloc(ctypes.byref(d), ctypes.c_void_p(src), ctypes.c_void_p(dst), step,
                                   block, grid, None, None)
