@@ -87,33 +87,40 @@ def time_steps(lat, steps, stream, torch):
 
 
 SETTLE_MS = 100.0  # GPU work queued right before every warm-up
-_settle_bufs = []
 
 
-def settle(stream, torch, ms=SETTLE_MS):
-    """Queue about `ms` milliseconds of device copies (1 GiB each, about
-    0.33 ms at the copy rate) on `stream`, without waiting for them.  The
-    GPU lowers its clocks when it idles (a 2 s pause made the next 20 steps
-    11 % slower, a tuning run with its synchronisations 3 %) and takes tens
-    of milliseconds to raise them again; the warm-up steps queued behind
-    these copies then start at steady clocks.  No lattice state is touched."""
-    if not _settle_bufs:
-        _settle_bufs.extend(torch.empty(1 << 30, dtype=torch.uint8, device="cuda") for _ in range(2))
-    a, c = _settle_bufs
-    with torch.cuda.stream(stream):
-        for _ in range(int(ms / 0.33) + 1):
-            c.copy_(a)
+def settle(scratch, est_ms_per_step, ms=SETTLE_MS):
+    """Queue about `ms` milliseconds of steps of `scratch`, a lattice (or
+    ensemble) of the same shape, storage and launch shape as the measured
+    one but with buffers of its own, on the measured one's stream, without
+    waiting for them.  The GPU lowers its clocks when it idles (a 2 s pause
+    made the next 20 steps 11 % slower) and takes tens of milliseconds to
+    raise them again; the warm-up steps queued behind this work then start
+    at the clocks the step kernel itself sustains (after 100 ms of plain
+    device copies instead, the first 20 timed steps behind a 5-step warm-up
+    were 1.5 % slower than the later ones).  The measured lattice is not
+    touched: it still takes exactly the requested warm-up steps."""
+    scratch.step(max(2, int(ms / est_ms_per_step) + 1))
+
+
+def est_ms(n_sites, storage, q=Q):
+    """Rough step time for sizing the settle work: the algorithmic bytes at
+    6 TB/s."""
+    return n_sites * bytes_per_site(storage, q) / 6e9
 
 
 def time_storage(storage, steps, warmup, stream, torch, tune=True, q=Q, in_place=False):
     from paper_2602_16486_amd import Lattice
     n = SHAPE[0] * SHAPE[1] * SHAPE[2]
-    with Lattice(q, SHAPE, storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED,
-                 stream=stream.cuda_stream, series_capacity=8192, in_place=in_place) as lat:
+    kw = dict(storage=storage, rho0=RHO0, tau=TAU, kT=KT, seed=SEED, stream=stream.cuda_stream,
+              in_place=in_place)
+    with Lattice(q, SHAPE, series_capacity=8192, **kw) as lat, \
+            Lattice(q, SHAPE, series_capacity=64, **kw) as scratch:
         if tune:
             lat.autotune(steps_per_trial=10)  # untimed; state restored
         launch = lat.launch
-        settle(stream, torch)
+        scratch.set_launch(*launch)
+        settle(scratch, est_ms(n, storage, q))
         lat.step(warmup)
         # the headline: exactly `steps` steps after the warm-up
         ms_step = time_steps(lat, steps, stream, torch)
@@ -156,15 +163,19 @@ def ensemble_run(steps, warmup, stream, torch, eq_steps=1000, tune=True):
         if tune:
             ens.autotune(steps_per_trial=4)
         tiles = ens.tiles
-        settle(stream, torch)
-        ens.step(warmup)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        ens.step(steps)
-        b.record(stream)
-        torch.cuda.synchronize()
+        # the scratch ensemble lives until the timed run is over (freeing it
+        # in between would idle the GPU)
+        with Ensemble(manifest, storage="f32", stream=stream.cuda_stream, series_capacity=64) as scratch:
+            scratch.set_tiles(*tiles)
+            settle(scratch, sum(est_ms(W.n_sites(r["shape"]), "f32", r["q"]) for r in manifest))
+            ens.step(warmup)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ens.step(steps)
+            b.record(stream)
+            torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
         kernel_ms = ens.profile_steps(10) / 10
         # equipartition per replica over the second half of eq_steps steps
@@ -384,8 +395,9 @@ def main():
                                                "CMF_ENSEMBLE_SPT27") if k in os.environ},
         },
         "timing": {
-            "protocol": f"autotuning (state restored), {SETTLE_MS:.0f} ms of device copies queued on the "
-                        f"lattice's stream (clocks up; no lattice state touched), {args.warmup} warm-up steps, "
+            "protocol": f"autotuning (state restored), about {SETTLE_MS:.0f} ms of steps of a scratch lattice of "
+                        f"the same shape and launch shape (buffers of its own; clocks up, the measured lattice "
+                        f"untouched) queued on the lattice's stream, {args.warmup} warm-up steps, "
                         f"then {args.steps} timed steps (the value); "
                         f"then {REPEATS} more timed runs of {args.steps} steps; CUDA/HIP events on "
                         f"the lattice's stream around cmf_step (32-step graph replays and direct "
