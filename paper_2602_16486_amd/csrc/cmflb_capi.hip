@@ -46,6 +46,12 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr double kCs2 = 1.0 / 3.0;
 constexpr int kGraphSteps = 32;
+// most steps whose statistics one forked reduction handles (lattices): the
+// partial sums go to a ring of 2 K slots, K = kStatBatch, or fewer steps
+// (down to 1) when the ring would exceed kStatRingBytes
+constexpr int kStatBatch = 8;
+constexpr size_t kStatRingBytes = (size_t)256 << 20;
+static_assert(kGraphSteps % kStatBatch == 0, "a captured run is whole batches");
 // noise counters are distinct for steps below 2^56 (see site_normals)
 constexpr int64_t kMaxStep = (int64_t)1 << 56;
 
@@ -190,11 +196,15 @@ void mode_constants(const cmf_desc *desc, ModeConstants &mc) {
   }
 }
 
-// Captured runs of kGraphSteps steps: step j passes step offset j and the
-// partial-sum buffer j mod 2 and runs on the caller's stream; its
-// statistics reduction runs on a second stream (default priority) once step
-// j is done, so it overlaps step j + 1; step j + 2 waits for it (it reuses
-// the buffer); the step counter advances once, after the last reduction.
+// Captured runs of kGraphSteps steps: step j passes step offset j and runs
+// on the caller's stream; the steps go in batches of K consecutive steps
+// (K = the lattice's stat_batch, at most kStatBatch; 1 for an ensemble),
+// step j writing its partial sums to slot j mod 2K; once a batch is done,
+// one statistics reduction for all its steps runs on a second stream
+// (default priority), overlapping the next batch; the first step of batch
+// b + 2 waits for it (it reuses the slots); the step counter advances once,
+// after the last reduction.  One fork per batch instead of one per step:
+// the event records and waits between the streams cost microseconds each.
 struct ForkedRun {
   hipStream_t aux = nullptr;
   hipEvent_t ev_step[kGraphSteps] = {};
@@ -228,54 +238,56 @@ int forked_init(ForkedRun &F) {
   return CMF_OK;
 }
 
-// Enqueue a run of n <= kGraphSteps steps in the forked form on stream s:
-// step(j, stream) enqueues step j (step offset j, partial-sum buffer j mod
-// 2); fin(j, stream) its statistics reduction (only when `stats`), on the
-// second stream; the step counter advances by n at the end.  Used inside a
-// graph capture (runs of kGraphSteps) and directly (the remainder of a
-// cmf_step call), so the statistics of direct steps overlap the next step
-// as well.
+// Enqueue a run of n <= kGraphSteps steps in the forked form on stream s,
+// in batches of K steps: step(j, stream) enqueues step j (step offset j,
+// partial-sum slot j mod 2K); fin(j0, count, stream) the statistics
+// reduction of steps j0 .. j0 + count - 1 (only when `stats`), on the second
+// stream; the step counter advances by n at the end.  Used inside a graph
+// capture (runs of kGraphSteps) and directly (the remainder of a cmf_step
+// call), so the statistics of direct steps overlap the next steps as well.
 template <class StepFn, class FinFn>
-hipError_t enqueue_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev,
+hipError_t enqueue_forked(hipStream_t s, ForkedRun &F, bool stats, int K, int64_t *step_dev,
                           StepFn step, FinFn fin, int n) {
   hipError_t e = hipSuccess;
-  for (int j = 0; j < n && e == hipSuccess; ++j) {
-    if (stats && j >= 2) e = hipStreamWaitEvent(s, F.ev_fin[j - 2], 0);
-    if (e == hipSuccess) e = step(j, s);
+  const int nbatch = (n + K - 1) / K;
+  for (int b = 0; b < nbatch && e == hipSuccess; ++b) {
+    const int j0 = b * K, j1 = j0 + K < n ? j0 + K : n;
+    if (stats && b >= 2) e = hipStreamWaitEvent(s, F.ev_fin[b - 2], 0);
+    for (int j = j0; j < j1 && e == hipSuccess; ++j) e = step(j, s);
     if (stats) {
-      if (e == hipSuccess) e = hipEventRecord(F.ev_step[j], s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(F.aux, F.ev_step[j], 0);
-      if (e == hipSuccess) e = fin(j, F.aux);
-      if (e == hipSuccess) e = hipEventRecord(F.ev_fin[j], F.aux);
+      if (e == hipSuccess) e = hipEventRecord(F.ev_step[b], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(F.aux, F.ev_step[b], 0);
+      if (e == hipSuccess) e = fin(j0, j1 - j0, F.aux);
+      if (e == hipSuccess) e = hipEventRecord(F.ev_fin[b], F.aux);
     }
   }
-  if (stats && e == hipSuccess) e = hipStreamWaitEvent(s, F.ev_fin[n - 1], 0);
+  if (stats && e == hipSuccess) e = hipStreamWaitEvent(s, F.ev_fin[nbatch - 1], 0);
   if (e == hipSuccess) e = launch_bump_step(step_dev, n, s);
   return e;
 }
 
 template <class StepFn, class FinFn>
-int run_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step, FinFn fin,
-               int n) {
+int run_forked(hipStream_t s, ForkedRun &F, bool stats, int K, int64_t *step_dev, StepFn step,
+               FinFn fin, int n) {
   if (n < 1 || n > kGraphSteps) return fail(CMF_EINVAL, "internal: forked run of %d steps", n);
   if (stats) {
     int rc = forked_init(F);
     if (rc != CMF_OK) return rc;
   }
-  const hipError_t e = enqueue_forked(s, F, stats, step_dev, step, fin, n);
+  const hipError_t e = enqueue_forked(s, F, stats, K, step_dev, step, fin, n);
   if (e != hipSuccess) return fail(CMF_EHIP, "step launch failed: %s", hipGetErrorString(e));
   return CMF_OK;
 }
 
 template <class StepFn, class FinFn>
-int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int64_t *step_dev, StepFn step,
-                   FinFn fin, hipGraphExec_t *out) {
+int capture_forked(hipStream_t s, ForkedRun &F, bool stats, int K, int64_t *step_dev,
+                   StepFn step, FinFn fin, hipGraphExec_t *out) {
   if (stats) {
     int rc = forked_init(F);
     if (rc != CMF_OK) return rc;
   }
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_forked(s, F, stats, step_dev, step, fin, kGraphSteps);
+  hipError_t e = enqueue_forked(s, F, stats, K, step_dev, step, fin, kGraphSteps);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(s, &g);
   if (e == hipSuccess) e = ec;
@@ -304,7 +316,9 @@ struct cmf_lattice {
   double *partials = nullptr;
   double *level2 = nullptr;
   int nparts = 0;
-  int partials_cap = 0;
+  int partials_cap = 0;    // partial rows per slot
+  int partials_slots = 0;  // slots allocated (2 stat_batch needed)
+  int stat_batch = 1;      // steps per forked statistics reduction
   int cus = 256;
   double *series = nullptr;
   int cap = 0;
@@ -477,14 +491,19 @@ int apply_launch(cmf_lattice *L, int block, int grid, const double *amp,
   L->block = block0;
   const int nt = pf.ntiles;
   const int g = grid < nt ? grid : nt;
-  if (g > L->partials_cap) {
+  const size_t slot_bytes = sizeof(double) * kPartStride * (size_t)g;
+  int K = kStatBatch;
+  while (K > 1 && 2 * (size_t)K * slot_bytes > kStatRingBytes) K /= 2;
+  if (g > L->partials_cap || 2 * K > L->partials_slots) {
     double *parts = nullptr;
-    if (hipMalloc((void **)&parts, 2 * sizeof(double) * kPartStride * g) != hipSuccess)
+    if (hipMalloc((void **)&parts, 2 * (size_t)K * slot_bytes) != hipSuccess)
       return fail(CMF_ENOMEM, "hipMalloc of the statistics partials failed");
     if (L->partials) (void)hipFree(L->partials);
     L->partials = parts;
     L->partials_cap = g;
+    L->partials_slots = 2 * K;
   }
+  L->stat_batch = K;
   L->block = block;
   L->pd = pd;
   L->pf = pf;
@@ -498,7 +517,7 @@ const void *step_params(const cmf_lattice *L) {
   return L->storage == kF64 ? (const void *)&L->pd : (const void *)&L->pf;
 }
 
-// partial-sum buffer b (0 or 1) of the lattice
+// partial-sum slot b (0 .. 2 stat_batch - 1) of the lattice
 double *partials_buf(const cmf_lattice *L, int b) {
   return L->partials + (size_t)b * kPartStride * L->partials_cap;
 }
@@ -556,33 +575,36 @@ int time_full_steps(cmf_lattice *L, int n, double *ms_out) {
 }
 
 // Steps of a forked run starting from buffer `parity` (step j reads
-// buf[parity ^ (j & 1)]) and their statistics reductions.
+// buf[parity ^ (j & 1)]) and the statistics reductions of their batches.
 struct LatticeRun {
   cmf_lattice *L;
   int parity;
   hipError_t operator()(int j, hipStream_t s) const {
-    return launch_lattice_step(L, parity ^ (j & 1), j, partials_buf(L, j & 1), s);
+    return launch_lattice_step(L, parity ^ (j & 1), j, partials_buf(L, j % (2 * L->stat_batch)), s);
   }
 };
 struct LatticeFin {
   cmf_lattice *L;
-  hipError_t operator()(int j, hipStream_t s) const {
-    return launch_finalize(partials_buf(L, j & 1), L->nparts, L->level2, L->series, L->cap,
-                           L->step_dev, j, 0, L->mass0, true, s);
+  hipError_t operator()(int j0, int count, hipStream_t s) const {
+    // j0 is a multiple of stat_batch: the batch's slots are consecutive
+    return launch_finalize_batch(partials_buf(L, j0 % (2 * L->stat_batch)),
+                                 (int64_t)kPartStride * L->partials_cap, count, L->nparts,
+                                 L->level2, L->series, L->cap, L->step_dev, j0, 0, L->mass0, true,
+                                 s);
   }
 };
 
 int capture_graph(cmf_lattice *L, int parity) {
   const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
-  return capture_forked(L->stream, L->forked, stats, L->step_dev, LatticeRun{L, parity},
-                        LatticeFin{L}, &L->graph[parity]);
+  return capture_forked(L->stream, L->forked, stats, L->stat_batch, L->step_dev,
+                        LatticeRun{L, parity}, LatticeFin{L}, &L->graph[parity]);
 }
 
 // n <= kGraphSteps direct steps in the forked form
 int run_direct(cmf_lattice *L, int n) {
   const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
-  int rc = run_forked(L->stream, L->forked, stats, L->step_dev, LatticeRun{L, L->parity},
-                      LatticeFin{L}, n);
+  int rc = run_forked(L->stream, L->forked, stats, L->stat_batch, L->step_dev,
+                      LatticeRun{L, L->parity}, LatticeFin{L}, n);
   if (rc == CMF_OK) L->parity ^= (n & 1);
   return rc;
 }
@@ -829,7 +851,8 @@ int create_lattice(const cmf_desc *desc, void *hip_stream, void *ext, size_t ext
     if (L->in_place) L->buf[1] = L->buf[0];
   }
   if (hipMalloc((void **)&L->series, sizeof(double) * kSeriesStride * L->cap) != hipSuccess ||
-      hipMalloc((void **)&L->level2, sizeof(double) * kPartStride * kMaxLevel2) != hipSuccess ||
+      hipMalloc((void **)&L->level2, sizeof(double) * kPartStride * kMaxLevel2 * kStatBatch) !=
+          hipSuccess ||
       hipMalloc((void **)&L->step_dev, sizeof(int64_t)) != hipSuccess) {
     release(L);
     return fail(CMF_ENOMEM, "hipMalloc of statistics buffers failed");
@@ -1674,7 +1697,8 @@ struct EnsembleRun {
 };
 struct EnsembleFin {
   cmf_ensemble *E;
-  hipError_t operator()(int j, hipStream_t s) const {
+  hipError_t operator()(int j, int count, hipStream_t s) const {
+    if (count != 1) return hipErrorInvalidValue;  // ensembles reduce step by step
     return launch_ensemble_finalize(E->storage, E->d_reps, E->n, ens_partials_buf(E, j & 1),
                                     E->series, E->cap, E->step_dev, j, 0, E->d_mass0, true, s);
   }
@@ -1682,13 +1706,13 @@ struct EnsembleFin {
 
 int ens_capture(cmf_ensemble *E, int parity) {
   const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
-  return capture_forked(E->stream, E->forked, stats, E->step_dev, EnsembleRun{E, parity},
+  return capture_forked(E->stream, E->forked, stats, 1, E->step_dev, EnsembleRun{E, parity},
                         EnsembleFin{E}, &E->graph[parity]);
 }
 
 int ens_run_direct(cmf_ensemble *E, int n) {
   const bool stats = !(E->flags & CMF_FLAG_NO_STATS);
-  int rc = run_forked(E->stream, E->forked, stats, E->step_dev, EnsembleRun{E, E->parity},
+  int rc = run_forked(E->stream, E->forked, stats, 1, E->step_dev, EnsembleRun{E, E->parity},
                       EnsembleFin{E}, n);
   if (rc == CMF_OK) E->parity ^= (n & 1);
   return rc;

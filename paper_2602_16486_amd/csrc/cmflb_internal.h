@@ -106,6 +106,14 @@ hipError_t launch_step(int q, int storage, bool general, bool nt, int mode,
 hipError_t launch_finalize(const double *partials, int nparts, double *level2,
                            double *series, int cap, int64_t *step_ptr, int step_off,
                            int bump, double mass0, bool stats, hipStream_t stream);
+// the statistics rows of `count` consecutive steps (step offsets step_off,
+// step_off + 1, ...) whose partial sums start at partials + k pstride
+// (k = 0 .. count - 1); level2 holds count kMaxLevel2 rows; bump must be 0
+// when count > 1
+hipError_t launch_finalize_batch(const double *partials, int64_t pstride, int count, int nparts,
+                                 double *level2, double *series, int cap, int64_t *step_ptr,
+                                 int step_off, int bump, double mass0, bool stats,
+                                 hipStream_t stream);
 hipError_t launch_bump_step(int64_t *step_ptr, int64_t by, hipStream_t stream);
 hipError_t launch_init_eq(int q, int storage, const ConvParams &cp,
                           const double *rho, const double *u, void *buf,

@@ -11,26 +11,31 @@ namespace cmf {
 // levels when there are many blocks) into the series row of the current
 // step, then advance the step counter
 // ---------------------------------------------------------------------------
-// first level: block r sums partial rows [r chunk, (r + 1) chunk)
+// first level: block (r, y) sums partial rows [r chunk, (r + 1) chunk) of
+// step y of a batch (its rows from partials + y pstride) into level-2 row
+// y gridDim.x + r
 __global__ __launch_bounds__(256) void k_reduce_partials(
-    const double *__restrict__ partials, int nparts, int chunk,
+    const double *__restrict__ partials, int nparts, int chunk, int64_t pstride,
     double *__restrict__ level2) {
   const int lo = blockIdx.x * chunk;
   const int hi = lo + chunk < nparts ? lo + chunk : nparts;
-  block_sum_rows(partials, lo, hi, level2 + (int64_t)blockIdx.x * kPartStride);
+  block_sum_rows(partials + blockIdx.y * pstride, lo, hi,
+                 level2 + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kPartStride);
 }
 
-// The statistics row of step *step_ptr + step_off; *step_ptr advances by
-// `bump` (0 inside a captured run of steps, which advances it once at its end).
+// The statistics row of step *step_ptr + step_off + y for block y of a
+// batch (its nrows rows from rows + y rstride); *step_ptr advances by `bump`
+// (0 inside a run of steps, which advances it once at its end; a batch of
+// more than one step passes 0).
 __global__ __launch_bounds__(256) void k_finalize(
-    const double *__restrict__ rows, int nrows, double *__restrict__ series,
+    const double *__restrict__ rows, int nrows, int64_t rstride, double *__restrict__ series,
     int cap, int64_t *__restrict__ step_ptr, int step_off, int bump, double mass0,
     int stats) {
   __shared__ double tot[kNAcc];
   const int64_t base = *step_ptr;
-  const int64_t step = base + step_off;
+  const int64_t step = base + step_off + blockIdx.x;
   if (stats) {
-    block_sum_rows(rows, 0, nrows, tot);
+    block_sum_rows(rows + blockIdx.x * rstride, 0, nrows, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
       double *row = series + (step % cap) * kSeriesStride;
@@ -497,21 +502,32 @@ hipError_t launch_step(int q, int storage, bool general, bool nt, int mode,
 hipError_t launch_finalize(const double *partials, int nparts, double *level2,
                            double *series, int cap, int64_t *step_ptr, int step_off,
                            int bump, double mass0, bool stats, hipStream_t stream) {
+  return launch_finalize_batch(partials, 0, 1, nparts, level2, series, cap, step_ptr, step_off,
+                               bump, mass0, stats, stream);
+}
+
+hipError_t launch_finalize_batch(const double *partials, int64_t pstride, int count, int nparts,
+                                 double *level2, double *series, int cap, int64_t *step_ptr,
+                                 int step_off, int bump, double mass0, bool stats,
+                                 hipStream_t stream) {
+  if (count < 1 || (count > 1 && bump != 0)) return hipErrorInvalidValue;
   const double *rows = partials;
   int nrows = nparts;
+  int64_t rstride = pstride;
   if (stats && nparts > kLevel2Threshold) {
     int nb = (nparts + kLevel2Threshold - 1) / kLevel2Threshold;
     if (nb > kMaxLevel2) nb = kMaxLevel2;
     const int chunk = (nparts + nb - 1) / nb;
     nb = (nparts + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, stream, partials,
-                       nparts, chunk, level2);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nb, count), dim3(256), 0, stream, partials,
+                       nparts, chunk, pstride, level2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     rows = level2;
     nrows = nb;
+    rstride = (int64_t)nb * kPartStride;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, rows, nrows,
+  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(256), 0, stream, rows, nrows, rstride,
                      series, cap, step_ptr, step_off, bump, mass0, stats ? 1 : 0);
   return hipGetLastError();
 }
