@@ -213,8 +213,10 @@ int cmf_step(cmf_lattice *lat, int64_t nsteps);
 /* Diagnostic timing: enqueue `nsteps` steps as direct launches (no graph)
  * with a HIP event pair around every fused-step kernel on the lattice's
  * stream, synchronise, and return in *kernel_ms the summed duration of the
- * step kernels alone (statistics finalize excluded), in milliseconds.  The
- * steps are real steps: the state and the statistics advance. */
+ * step kernels alone, in milliseconds (the statistics reductions run after
+ * each batch of up to 8 steps, outside the event pairs, so that only the
+ * event markers separate consecutive kernels).  The steps are real steps:
+ * the state and the statistics advance. */
 int cmf_profile_steps(cmf_lattice *lat, int64_t nsteps, double *kernel_ms);
 
 /* One launch shape of the fused-step kernel: `block` threads per workgroup

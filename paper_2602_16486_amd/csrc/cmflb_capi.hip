@@ -1014,15 +1014,26 @@ int cmf_profile_steps(cmf_lattice *L, int64_t nsteps, double *kernel_ms) {
   std::vector<hipEvent_t> ev(2 * nsteps, nullptr);
   int rc = create_events(ev);
   if (rc != CMF_OK) return rc;
-  for (int64_t s = 0; s < nsteps && rc == CMF_OK; ++s) {
-    hipError_t e = hipEventRecord(ev[2 * s], L->stream);
-    if (e == hipSuccess) e = launch_lattice_step(L, L->parity, 0, partials_buf(L, 0), L->stream);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], L->stream);
-    if (e == hipSuccess)
-      e = launch_finalize(partials_buf(L, 0), L->nparts, L->level2, L->series, L->cap, L->step_dev,
-                          0, 1, L->mass0, !(L->desc.flags & CMF_FLAG_NO_STATS), L->stream);
+  // batches of stat_batch steps, each kernel between its own event pair and
+  // the batch's statistics reduction after the batch, so that only event
+  // markers separate consecutive step kernels
+  const int K = L->stat_batch;
+  const bool stats = !(L->desc.flags & CMF_FLAG_NO_STATS);
+  for (int64_t s0 = 0; s0 < nsteps && rc == CMF_OK; s0 += K) {
+    const int cnt = nsteps - s0 < K ? (int)(nsteps - s0) : K;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < cnt && e == hipSuccess; ++j) {
+      e = hipEventRecord(ev[2 * (s0 + j)], L->stream);
+      if (e == hipSuccess) e = launch_lattice_step(L, L->parity, j, partials_buf(L, j), L->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * (s0 + j) + 1], L->stream);
+      if (e == hipSuccess) L->parity ^= 1;
+    }
+    if (e == hipSuccess && stats)
+      e = launch_finalize_batch(partials_buf(L, 0), (int64_t)kPartStride * L->partials_cap, cnt,
+                                L->nparts, L->level2, L->series, L->cap, L->step_dev, 0, 0,
+                                L->mass0, true, L->stream);
+    if (e == hipSuccess) e = launch_bump_step(L->step_dev, cnt, L->stream);
     if (e != hipSuccess) rc = fail(CMF_EHIP, "profiled step failed: %s", hipGetErrorString(e));
-    L->parity ^= 1;
   }
   hipError_t e = hipStreamSynchronize(L->stream);
   if (rc == CMF_OK && e != hipSuccess) rc = fail(CMF_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));

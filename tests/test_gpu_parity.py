@@ -357,6 +357,30 @@ def test_tune_cache_file_round_trip(tmp_path):
     assert first == default
 
 
+@pytest.mark.parametrize("q,shape,in_place", [(27, (40, 12, 10), False), (27, (40, 12, 10), True),
+                                              (9, (70, 40), False)])
+def test_profiled_steps_are_real_steps(q, shape, in_place):
+    """cmf_profile_steps times direct launches with their statistics
+    reduced after batches of steps: the state, every statistics row and the
+    step counter advance exactly as with cmf_step (runs that end inside a
+    batch included)."""
+    f0 = _random_state(q, shape, 61)
+    kw = dict(storage="f32", kT=1e-4, seed=8, in_place=in_place)
+    with Lattice(q, shape, **kw) as lat, Lattice(q, shape, flags=_lib.FLAG_NO_GRAPH, **kw) as ref:
+        lat.set_populations(f0)
+        ref.set_populations(f0)
+        lat.step(3)
+        assert lat.profile_steps(11) > 0.0
+        lat.step(2)
+        assert lat.profile_steps(19) > 0.0
+        ref.step(35)
+        assert lat.step_index == ref.step_index == 35
+        assert np.array_equal(lat.get_populations(), ref.get_populations())
+        st, st_ref = lat.stats(), ref.stats()
+        assert np.array_equal(st[:, 0], np.arange(35))
+        assert np.array_equal(st, st_ref)
+
+
 def test_empty_calls_are_no_ops():
     """Zero steps, an empty site list, a statistics read with no new step and
     a zero-step profile change nothing; the next real step is step 0's
