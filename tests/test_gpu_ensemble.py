@@ -111,6 +111,30 @@ def test_graph_replay_equals_direct_launches():
         assert np.array_equal(a, b)
 
 
+def test_profiled_steps_are_real_steps():
+    """cmf_ensemble_profile_steps (statistics reduced after batches of
+    steps) advances every replica, its statistics rows and the step counter
+    exactly like cmf_ensemble_step."""
+    states = [_state(r, 250 + k) for k, r in enumerate(REPLICAS)]
+    out = []
+    for profiled in (True, False):
+        with Ensemble(REPLICAS, storage="f32", flags=0 if profiled else _lib.FLAG_NO_GRAPH) as ens:
+            for k, f in enumerate(states):
+                ens.set_populations(k, f)
+            if profiled:
+                ens.step(3)
+                assert ens.profile_steps(11) > 0.0
+                ens.step(2)
+                assert ens.profile_steps(19) > 0.0
+            else:
+                ens.step(35)
+            assert ens.step_index == 35
+            out.append([ens.get_populations(k) for k in range(len(REPLICAS))] +
+                       [ens.stats(k) for k in range(len(REPLICAS))])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_general_rates_replica_and_rest_replicas():
     """A replica with a non-paper rate vector switches the ensemble to the
     general kernel; the other replicas are unaffected (the general kernel with
