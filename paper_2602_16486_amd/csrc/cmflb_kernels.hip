@@ -34,7 +34,10 @@ __global__ __launch_bounds__(256) void k_finalize(
   __shared__ double tot[kNAcc];
   const int64_t base = *step_ptr;
   const int64_t step = base + step_off + blockIdx.x;
-  if (stats) {
+  // with a ring shorter than the batch, a later step of the same batch
+  // takes the same row: only the latest of them writes it, as if the steps
+  // had been reduced one after the other
+  if (stats && blockIdx.x + (int64_t)cap >= gridDim.x) {
     block_sum_rows(rows + blockIdx.x * rstride, 0, nrows, tot);
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -381,6 +381,30 @@ def test_profiled_steps_are_real_steps(q, shape, in_place):
         assert np.array_equal(st, st_ref)
 
 
+@pytest.mark.parametrize("cap", [1, 3, 7])
+def test_short_statistics_ring_keeps_the_latest_steps(cap):
+    """A statistics ring shorter than the batch of steps whose statistics
+    are reduced together keeps the most recent rows, as one reduction per
+    step would: direct calls (batches of 8, 8, 4 steps), graph replays and
+    profiled steps, read after each call."""
+    q, shape = 27, (30, 10, 8)
+    f0 = _random_state(q, shape, 91)
+    kw = dict(storage="f32", kT=1e-4, seed=4)
+    with Lattice(q, shape, series_capacity=cap, **kw) as lat, Lattice(q, shape, **kw) as ref:
+        lat.set_populations(f0)
+        ref.set_populations(f0)
+        for call in ("step 20", "step 37", "profile 11", "step 5"):
+            kind, n = call.split()
+            for x in (lat, ref):
+                if kind == "step":
+                    x.step(int(n))
+                else:
+                    x.profile_steps(int(n))
+            got, want = lat.stats(), ref.stats()
+            assert len(want) == int(n) and len(got) == min(cap, int(n)), call
+            assert np.array_equal(got, want[-cap:]), call
+
+
 def test_empty_calls_are_no_ops():
     """Zero steps, an empty site list, a statistics read with no new step and
     a zero-step profile change nothing; the next real step is step 0's
