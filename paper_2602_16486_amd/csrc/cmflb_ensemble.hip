@@ -134,7 +134,8 @@ __global__ __launch_bounds__(kEnsembleBlock) void k_ensemble_step(
       if (s < end) ensemble_site<D2Q9, S, R, GENERAL>(rs, rd, p, s, step, acc);
     }
   }
-  block_store_acc_shuffle(acc, partials + (int64_t)tile * kPartStride);
+  __shared__ double acc_lds[acc_lds_bytes<double>(kEnsembleBlock) / sizeof(double)];
+  block_store_acc(acc, partials + (int64_t)tile * kPartStride, acc_lds);
 }
 
 // per-replica fixed-order sum of its tiles' partials into its series row
